@@ -63,6 +63,8 @@ def lib() -> ctypes.CDLL:
         L.oracle_force.restype = None
         L.oracle_force_sliced.argtypes = [i64, p, p, p, f64, i64, i64, p, p, p, p]
         L.oracle_force_sliced.restype = None
+        L.oracle_force_abs.argtypes = [i64, p, p, p, f64, i64, p, p]
+        L.oracle_force_abs.restype = None
         L.oracle_predict.argtypes = [i64, p, p, p, p, p, f64, p, p]
         L.oracle_predict.restype = None
         L.oracle_correct_one.argtypes = [f64, p, p, p, p, p, p, p, p, p, p]
@@ -120,6 +122,17 @@ def force(m, x, v, eps: float, active=None, slices: int | None = None):
         lib().oracle_force_sliced(n, _ptr(m), _ptr(x), _ptr(v), float(eps), int(slices), na,
                                   _ptr(act), _ptr(acc), _ptr(jerk), _ptr(pot))
     return acc, jerk, pot
+
+
+def force_abs(m, x, v, eps: float, active=None) -> np.ndarray:
+    """(3, n_act): sums of |acceleration term|, |jerk term| and |potential
+    term| over j -- the scale that rounding errors are measured against."""
+    m, x, v = _f64(m), _f64(x), _f64(v)
+    n = m.shape[0]
+    act = np.arange(n, dtype=np.int32) if active is None else np.ascontiguousarray(active, dtype=np.int32)
+    out = np.zeros((3, act.shape[0]))
+    lib().oracle_force_abs(n, _ptr(m), _ptr(x), _ptr(v), float(eps), act.shape[0], _ptr(act), _ptr(out))
+    return out
 
 
 def predict(x, v, a, k, t, t_pred: float):

@@ -126,6 +126,36 @@ void oracle_force_sliced(int64_t n, const double *m, const double *x, const doub
     }
 }
 
+/* Sums of the absolute pair terms on each active particle, the scale that
+ * rounding errors of any summation order are measured against:
+ * out[0][q] = sum m_j |r_ij| / R^3 (acceleration), out[1][q] = sum of
+ * |jerk term|, out[2][q] = sum m_j / R (potential).  out: [3][n_act]. */
+void oracle_force_abs(int64_t n, const double *m, const double *x, const double *v, double eps,
+                      int64_t n_act, const int32_t *act, double *out) {
+    const double eps2 = eps * eps;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t q = 0; q < n_act; ++q) {
+        const int64_t i = act[q];
+        double sa = 0.0, sk = 0.0, sp = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            const double dx = x[j] - x[i], dy = x[n + j] - x[n + i], dz = x[2 * n + j] - x[2 * n + i];
+            const double dvx = v[j] - v[i], dvy = v[n + j] - v[n + i], dvz = v[2 * n + j] - v[2 * n + i];
+            const double r2 = dx * dx + dy * dy + dz * dz + eps2;
+            const double rinv = 1.0 / sqrt(r2);
+            const double mr3 = m[j] * rinv * rinv * rinv;
+            const double c = 3.0 * (dx * dvx + dy * dvy + dz * dvz) * rinv * rinv;
+            const double wx = dvx - c * dx, wy = dvy - c * dy, wz = dvz - c * dz;
+            sa += mr3 * sqrt(dx * dx + dy * dy + dz * dz);
+            sk += mr3 * sqrt(wx * wx + wy * wy + wz * wz);
+            sp += m[j] * rinv;
+        }
+        out[q] = sa;
+        out[n_act + q] = sk;
+        out[2 * n_act + q] = sp;
+    }
+}
+
 /* ---------------------------------------------------------------------- */
 /* Hermite predictor (Sect. 2.1, predictor equations).                    */
 
