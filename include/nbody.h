@@ -1,0 +1,219 @@
+/*
+ * nbody.h -- C ABI of libnbody, a direct-summation N-body engine for AMD
+ * Instinct MI355X (gfx950).
+ *
+ * The library advances one or more independent star clusters with the
+ * fourth-order Hermite predictor-corrector and power-of-two block time
+ * steps described in Portegies Zwart, McMillan, Groen, Gualandris, Sipior &
+ * Vermin, "A parallel gravitational N-body kernel" (New Astronomy, 2008),
+ * Sect. 2.1.  Its hot path is the O(n_act * N) pairwise evaluation of
+ * acceleration, jerk and potential on the active block against every
+ * predicted particle of the same cluster.
+ *
+ * Conventions shared by every call:
+ *   - G = 1; N-body units are expected but not enforced.
+ *   - Particle arrays are structure-of-arrays FP64: a vector array v of n
+ *     particles holds v[0*n+i], v[1*n+i], v[2*n+i] for the x, y, z
+ *     components of particle i.  Outputs for an active list use n_active in
+ *     place of n and follow the order of the active list.
+ *   - Particles are numbered globally 0..n_total-1; cluster c owns the
+ *     contiguous range [cluster_offsets[c], cluster_offsets[c+1]).  Clusters
+ *     never interact.
+ *   - Memory: the caller owns every device buffer, including the workspace
+ *     that holds the whole simulation state.  The library never allocates or
+ *     frees device memory; nbody_destroy frees only the host-side context.
+ *   - Streams: every call that takes a context is enqueued on the context's
+ *     HIP stream and returns before the GPU work finishes, unless stated.
+ *     Host-side validation errors are returned synchronously and enqueue
+ *     nothing.  Errors detected on the device (step underflow, non-finite
+ *     values, out-of-range indices) are recorded in a status word in the
+ *     workspace, returned by nbody_sync and by the next call that reads it.
+ *   - A context is bound to one stream and is not thread-safe.
+ *
+ * Readings of the paper the library implements (the paper does not spell
+ * these out): the pair vector is x_j - x_i (Eq. Force prints the repulsive
+ * sign); Plummer softening R^2 = |x_j - x_i|^2 + eps^2 in acceleration, jerk
+ * and potential; the jerk is the exact time derivative of the softened
+ * acceleration; phi_i = -sum_{j != i} m_j / R; Aarseth's criterion
+ * (Eq. timestep) uses the end-of-step |a|, |a2 + a3 dt|, |k|, |a3|; new
+ * steps are rounded down to a power of two, may shrink freely, at most
+ * double and only when the current time is a multiple of the doubled step,
+ * and are capped at dt_max; initial steps are eta_init |a|/|k| rounded down.
+ */
+#ifndef NBODY_H
+#define NBODY_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#if defined(__GNUC__) || defined(__clang__)
+#define NBODY_API __attribute__((visibility("default")))
+#else
+#define NBODY_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct nbody_ctx nbody_ctx;
+
+typedef enum {
+    NBODY_OK = 0,
+    NBODY_E_INVAL = -1,     /* bad argument (host-side validation)               */
+    NBODY_E_NOMEM = -2,     /* workspace too small / host allocation failed      */
+    NBODY_E_HIP = -3,       /* a HIP runtime call failed                         */
+    NBODY_E_STATE = -4,     /* call out of order (e.g. correct before predict)   */
+    NBODY_E_DTMIN = -5,     /* device: a new step fell below dt_min              */
+    NBODY_E_NONFINITE = -6, /* device: non-finite position, velocity or force    */
+    NBODY_E_INDEX = -7      /* device: active index outside its cluster or
+                               active offsets not monotonic                      */
+} nbody_status;
+
+/* Arithmetic of the pairwise kernel.
+ *   NBODY_FP64:  plain FP64 throughout.
+ *   NBODY_MIXED: positions differenced in extended precision (FP64 or
+ *                double-single), pair terms in FP32, partial sums over short
+ *                j-windows in FP32 flushed into FP64 totals.  Predictor,
+ *                corrector and time steps stay FP64 in both modes. */
+typedef enum { NBODY_FP64 = 0, NBODY_MIXED = 1 } nbody_precision;
+
+typedef struct {
+    double eta;          /* Aarseth accuracy parameter nu (Sect. 2.1: 0.01)      */
+    double eta_init;     /* initial step eta_init*|a|/|k| (0.01)                 */
+    double dt_max;       /* largest step, a power of two (2^-3)                  */
+    double dt_min;       /* smallest allowed step (2^-40); below: NBODY_E_DTMIN  */
+    int32_t precision;   /* nbody_precision                                      */
+    int32_t compute_pot; /* nonzero: nbody_step also keeps phi of the block      */
+} nbody_params;
+
+/* Fills *p with the defaults given in parentheses above (FP64, no pot). */
+NBODY_API void nbody_default_params(nbody_params *p);
+
+/* Bytes of device workspace needed for n_total particles in n_clusters
+ * clusters.  Pure host computation; never fails for valid sizes
+ * (n_total >= 1, 1 <= n_clusters <= n_total, n_total < 2^31). */
+NBODY_API nbody_status nbody_workspace_bytes(int64_t n_total, int32_t n_clusters, const nbody_params *p,
+                                   size_t *bytes);
+
+/* Creates a context and starts the integration (Sect. 2.1: every particle
+ * gets a and k by direct summation, t_i = 0 and its initial step).
+ *   cluster_offsets: host, n_clusters+1 ascending entries, [0] = 0,
+ *                    [n_clusters] = n_total, every cluster non-empty.
+ *   m (host, n_total), x, v (host, [3][n_total]): initial state.
+ *   eps: host, n_clusters softening lengths (>= 0).
+ *   workspace: device, at least nbody_workspace_bytes(), 256-byte aligned,
+ *              owned by the caller and kept alive until nbody_destroy.
+ *   hip_stream: a hipStream_t (NULL = the default stream).
+ * Copies the host arrays (synchronously with respect to the host arrays:
+ * they may be freed on return) and enqueues the start-up force pass. */
+NBODY_API nbody_status nbody_init(nbody_ctx **ctx, int64_t n_total, int32_t n_clusters,
+                        const int64_t *cluster_offsets, const double *m, const double *x,
+                        const double *v, const double *eps, const nbody_params *p,
+                        void *workspace, size_t workspace_bytes, void *hip_stream);
+
+/* Replaces the parameters (e.g. switches precision).  dt_max/dt_min changes
+ * take effect at the next step. */
+NBODY_API nbody_status nbody_set_params(nbody_ctx *ctx, const nbody_params *p);
+
+/* Hermite predictor (Sect. 2.1, predictor equations): predicts every
+ * particle of cluster c to time t_pred[c] (host array, n_clusters entries),
+ * giving x_p, v_p in FP64 and the record the mixed kernel reads.  NULL
+ * predicts every cluster to its current time (x_p = x, v_p = v). */
+NBODY_API nbody_status nbody_predict(nbody_ctx *ctx, const double *t_pred);
+
+/* Pairwise acceleration, jerk and (optionally) potential (Sect. 2.1,
+ * Eq. Force and the jerk by direct summation) on the listed particles from
+ * every predicted particle j != i of the same cluster.
+ *   active_idx: device, n_active global particle ids, cluster-major and
+ *               ascending inside each cluster.
+ *   active_offsets: device, n_clusters+1 int64; the entries of cluster c are
+ *               active_idx[active_offsets[c] .. active_offsets[c+1]).
+ *   acc, jerk: device, [3][n_active] FP64 outputs; pot: device [n_active]
+ *              or NULL.
+ * Uses the context's precision.  Indices outside their cluster set
+ * NBODY_E_INDEX on the device and produce zeros for that entry. */
+NBODY_API nbody_status nbody_force(nbody_ctx *ctx, const int32_t *active_idx, const int64_t *active_offsets,
+                         int64_t n_active, double *acc, double *jerk, double *pot);
+
+/* Hermite corrector, Aarseth step and block quantisation (Sect. 2.1) for the
+ * listed particles, advancing each to its cluster's last predicted time.
+ * acc, jerk: device [3][n_active], the values at the predicted time (as
+ * returned by nbody_force on the same list). */
+NBODY_API nbody_status nbody_correct(nbody_ctx *ctx, const int32_t *active_idx,
+                           const int64_t *active_offsets, int64_t n_active, const double *acc,
+                           const double *jerk);
+
+/* Up to n_block_steps block steps (Sect. 2.1 item list: select the particles
+ * with the smallest t_i + dt_i, predict all, force on the block, correct,
+ * new steps).  Each step advances every cluster whose time is below t_end by
+ * exactly one of its own block steps; clusters at t_end stay put.  t_end
+ * must be a multiple of dt_max.  Runs as a captured HIP graph, replayed
+ * n_block_steps times without host synchronisation. */
+NBODY_API nbody_status nbody_step(nbody_ctx *ctx, int32_t n_block_steps, double t_end);
+
+/* Waits for the context's stream; returns the first device-side error. */
+NBODY_API nbody_status nbody_sync(nbody_ctx *ctx);
+
+/* Per-cluster softened energy E = sum m v^2/2 + (1/2) sum m phi in FP64,
+ * written to E_host (n_clusters).  Synchronous.  Meaningful only when every
+ * particle of a cluster is at the same time (multiples of dt_max). */
+NBODY_API nbody_status nbody_energy(nbody_ctx *ctx, double *E_host);
+
+/* Per-cluster progress, synchronous: time of the last block step, number of
+ * block steps taken and pairwise interactions evaluated (block size times
+ * cluster size, summed).  Any pointer may be NULL. */
+NBODY_API nbody_status nbody_progress(nbody_ctx *ctx, double *t_host, int64_t *steps_host,
+                            double *interactions_host);
+
+/* Checkpoint: bytes of the state blob, and copies of the full FP64 state
+ * (m, x, v, a, k, t, dt, softening, cluster times and counters) to / from a
+ * host buffer.  Synchronous.  Restoring and continuing gives the same bits
+ * as an uninterrupted run. */
+NBODY_API nbody_status nbody_state_bytes(const nbody_ctx *ctx, size_t *bytes);
+NBODY_API nbody_status nbody_get_state(nbody_ctx *ctx, void *host_buf, size_t bytes);
+NBODY_API nbody_status nbody_set_state(nbody_ctx *ctx, const void *host_buf, size_t bytes);
+
+/* Byte offsets, inside the workspace, of the FP64 state arrays, so the owner
+ * of the workspace can read them in place (e.g. as tensors). */
+typedef struct {
+    int64_t n_total;
+    int32_t n_clusters;
+    int32_t reserved;
+    size_t m, x, v, a, k, t, dt; /* [n], [3][n], [3][n], [3][n], [3][n], [n], [n] */
+    size_t xp, vp;               /* predicted state, [3][n] each                 */
+    size_t pot;                  /* potential of the last block (compute_pot)    */
+} nbody_layout;
+NBODY_API nbody_status nbody_get_layout(const nbody_ctx *ctx, nbody_layout *out);
+
+/* Launch tuning of the force pass.  Results for a cluster depend only on
+ * its own size, its block size and these values (never on other clusters
+ * in the batch); changing them changes force sums at rounding level only.
+ *   target_items: work items (i-chunk x j-slice) a cluster's force pass is
+ *                 split into when it has enough tiles (default: 8 per CU).
+ *   min_block: smallest block size that uses the 1-, 4- and 16-lane-per-i
+ *              layouts (default 192, 48, 12); smaller blocks use 64 lanes
+ *              per i.  Must be non-increasing and >= 1.
+ *   grid: persistent workgroups of the force launch (default: 8 per CU).
+ *   mixed_format: positions of the mixed kernel as double-single FP32
+ *                 pairs (0, default) or FP64 (1). */
+typedef struct {
+    int32_t target_items;
+    int32_t min_block[3];
+    int32_t grid;
+    int32_t mixed_format;
+} nbody_tuning;
+NBODY_API nbody_status nbody_get_tuning(const nbody_ctx *ctx, nbody_tuning *out);
+NBODY_API nbody_status nbody_set_tuning(nbody_ctx *ctx, const nbody_tuning *t);
+
+/* Frees the host context (never the workspace).  NULL is accepted. */
+NBODY_API nbody_status nbody_destroy(nbody_ctx *ctx);
+
+/* Static description of a status code. */
+NBODY_API const char *nbody_strerror(nbody_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NBODY_H */

@@ -1,0 +1,567 @@
+// Host side of libnbody: the C ABI declared in include/nbody.h.
+//
+// The library owns no device memory: nbody_init carves the caller's
+// workspace into the arrays of DevState, and every call enqueues kernels on
+// the context's stream.  nbody_step captures one block step (select ->
+// plan -> force -> correct) into a HIP graph once and replays it.
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "common.h"
+#include "kernels.h"
+#include "nbody.h"
+
+using namespace nb;
+
+namespace {
+
+constexpr uint32_t kStateMagic = 0x5453424eu;  // "NBST"
+constexpr uint32_t kStateVersion = 1;
+
+struct Layout {
+  size_t coff, eps, cid, ch_cluster, ch_begin, cl_ch;
+  size_t m, x, v, a, k, t, dt, xp, vp, pot, jr;
+  size_t tpred, tnow, tsys, inter, steps, cmin, ccount, act, aoff, plan, ctl, part, fout, status, eout;
+  size_t total;
+  int64_t rows_cap;
+  int64_t nch_max;
+};
+
+size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
+
+Layout make_layout(int64_t n, int32_t nc) {
+  Layout L{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = align_up(o + bytes);
+    return at;
+  };
+  const size_t N = (size_t)n, C = (size_t)nc;
+  L.nch_max = n / kSelChunk + nc;
+  L.rows_cap = kRowsPerParticle * n + kRowsPerCluster * (int64_t)nc;
+  L.coff = take(8 * (C + 1));
+  L.eps = take(8 * C);
+  L.cid = take(4 * N);
+  L.ch_cluster = take(4 * (size_t)L.nch_max);
+  L.ch_begin = take(8 * ((size_t)L.nch_max + 1));
+  L.cl_ch = take(4 * (C + 1));
+  L.m = take(8 * N);
+  L.x = take(24 * N);
+  L.v = take(24 * N);
+  L.a = take(24 * N);
+  L.k = take(24 * N);
+  L.t = take(8 * N);
+  L.dt = take(8 * N);
+  L.xp = take(24 * N);
+  L.vp = take(24 * N);
+  L.pot = take(8 * N);
+  L.jr = take(4 * JR_ROWS * N);
+  L.tpred = take(8 * C);
+  L.tnow = take(8 * C);
+  L.tsys = take(8 * C);
+  L.inter = take(8 * C);
+  L.steps = take(8 * C);
+  L.cmin = take(8 * (size_t)L.nch_max);
+  L.ccount = take(4 * (size_t)L.nch_max);
+  L.act = take(4 * N);
+  L.aoff = take(8 * (C + 1));
+  L.plan = take(sizeof(Plan) * C);
+  L.ctl = take(sizeof(Ctl));
+  L.part = take(8 * 7 * (size_t)L.rows_cap);
+  L.fout = take(8 * 7 * N);
+  L.status = take(4);
+  L.eout = take(8 * C);
+  L.total = o;
+  return L;
+}
+
+bool valid_params(const nbody_params* p) {
+  if (!p) return false;
+  if (!(p->eta > 0.0) || !isfinite(p->eta)) return false;
+  if (!(p->eta_init > 0.0) || !isfinite(p->eta_init)) return false;
+  if (!(p->dt_max > 0.0) || !isfinite(p->dt_max)) return false;
+  if (!(p->dt_min > 0.0) || !(p->dt_min <= p->dt_max)) return false;
+  int e;
+  if (frexp(p->dt_max, &e) != 0.5) return false;  // dt_max must be a power of two
+  if (p->precision != NBODY_FP64 && p->precision != NBODY_MIXED) return false;
+  return true;
+}
+
+}  // namespace
+
+struct nbody_ctx {
+  DevState s{};
+  Layout L{};
+  nbody_params p{};
+  hipStream_t stream = nullptr;
+  hipStream_t cap_stream = nullptr;  // private stream used only for graph capture
+  unsigned char* ws = nullptr;
+  int64_t n = 0;
+  int32_t nc = 0;
+  int32_t nch = 0;
+  int grid = 2048;        // persistent force grid
+  int target_items = 2048;  // work items a force pass aims at per cluster
+  int mixed_mode = kDS;   // position format of the mixed kernel
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  int graph_mode = -1;    // force mode the graph was captured with
+  int graph_pot = -1;
+  bool predicted = false;
+  std::vector<int64_t> coff;
+  Ctl ctl{};
+};
+
+namespace {
+
+#define HIP_OK(expr)                          \
+  do {                                        \
+    if ((expr) != hipSuccess) return NBODY_E_HIP; \
+  } while (0)
+
+int force_mode(const nbody_ctx* c) { return c->p.precision == NBODY_FP64 ? kF64 : c->mixed_mode; }
+
+nbody_status upload_ctl(nbody_ctx* c) {
+  c->ctl.eta = c->p.eta;
+  c->ctl.eta_init = c->p.eta_init;
+  c->ctl.dt_max = c->p.dt_max;
+  c->ctl.dt_min = c->p.dt_min;
+  c->ctl.compute_pot = c->p.compute_pot ? 1 : 0;
+  HIP_OK(hipMemcpyAsync(c->ws + c->L.ctl, &c->ctl, sizeof(Ctl), hipMemcpyHostToDevice, c->stream));
+  HIP_OK(hipStreamSynchronize(c->stream));  // c->ctl is host memory the copy reads
+  return NBODY_OK;
+}
+
+nbody_status status_from_bits(int32_t bits) {
+  if (bits & ST_INDEX) return NBODY_E_INDEX;
+  if (bits & ST_NONFINITE) return NBODY_E_NONFINITE;
+  if (bits & ST_DTMIN) return NBODY_E_DTMIN;
+  if (bits & ST_STATE) return NBODY_E_STATE;
+  return NBODY_OK;
+}
+
+// Force on the internal identity active list into s.fout (start-up, energy).
+nbody_status force_all_internal(nbody_ctx* c, int mode) {
+  const DevState& s = c->s;
+  HIP_OK(launch_identity(s, c->stream));
+  HIP_OK(launch_plan(s, s.aoff, s.n, c->target_items, c->stream));
+  HIP_OK(launch_force(s, mode, s.act, c->grid, c->stream));
+  HIP_OK(launch_reduce(s, s.aoff, s.n, s.fout, s.fout + 3 * s.n, s.fout + 6 * s.n, c->stream));
+  return NBODY_OK;
+}
+
+void destroy_graph(nbody_ctx* c) {
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  c->gexec = nullptr;
+  c->graph = nullptr;
+  c->graph_mode = -1;
+}
+
+nbody_status build_graph(nbody_ctx* c) {
+  destroy_graph(c);
+  const DevState& s = c->s;
+  const int mode = force_mode(c);
+  if (!c->cap_stream) HIP_OK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+  HIP_OK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed));
+  hipError_t e = launch_select(s, c->cap_stream);
+  if (e == hipSuccess) e = launch_plan(s, s.aoff, s.n, c->target_items, c->cap_stream, 1);
+  if (e == hipSuccess) e = launch_force(s, mode, s.act, c->grid, c->cap_stream);
+  if (e == hipSuccess) e = launch_correct(s, s.act, s.aoff, s.n, nullptr, nullptr, 1, c->cap_stream);
+  hipGraph_t g = nullptr;
+  const hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
+  if (e != hipSuccess || e2 != hipSuccess || !g) {
+    if (g) (void)hipGraphDestroy(g);
+    return NBODY_E_HIP;
+  }
+  c->graph = g;
+  if (hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0) != hipSuccess) {
+    destroy_graph(c);
+    return NBODY_E_HIP;
+  }
+  c->graph_mode = mode;
+  c->graph_pot = c->p.compute_pot;
+  return NBODY_OK;
+}
+
+}  // namespace
+
+namespace {
+struct Part {
+  size_t off;    // device offset in the workspace
+  size_t bytes;
+};
+std::vector<Part> state_parts(const nbody_ctx* c) {
+  const size_t N = (size_t)c->n, C = (size_t)c->nc;
+  const Layout& L = c->L;
+  return {{L.coff, 8 * (C + 1)}, {L.eps, 8 * C}, {L.m, 8 * N},   {L.x, 24 * N},    {L.v, 24 * N},
+          {L.a, 24 * N},         {L.k, 24 * N},  {L.t, 8 * N},   {L.dt, 8 * N},    {L.tnow, 8 * C},
+          {L.inter, 8 * C},      {L.steps, 8 * C}};
+}
+}  // namespace
+
+extern "C" {
+
+void nbody_default_params(nbody_params* p) {
+  if (!p) return;
+  p->eta = 0.01;
+  p->eta_init = 0.01;
+  p->dt_max = 0.125;
+  p->dt_min = ldexp(1.0, -40);
+  p->precision = NBODY_FP64;
+  p->compute_pot = 0;
+}
+
+nbody_status nbody_workspace_bytes(int64_t n_total, int32_t n_clusters, const nbody_params* p, size_t* bytes) {
+  (void)p;
+  if (!bytes || n_total < 1 || n_total >= ((int64_t)1 << 31) - 1 || n_clusters < 1 || n_clusters > n_total)
+    return NBODY_E_INVAL;
+  *bytes = make_layout(n_total, n_clusters).total;
+  return NBODY_OK;
+}
+
+nbody_status nbody_init(nbody_ctx** out, int64_t n_total, int32_t n_clusters, const int64_t* cluster_offsets,
+                        const double* m, const double* x, const double* v, const double* eps,
+                        const nbody_params* p, void* workspace, size_t workspace_bytes, void* hip_stream) {
+  if (!out) return NBODY_E_INVAL;
+  *out = nullptr;
+  if (!cluster_offsets || !m || !x || !v || !eps || !workspace || !valid_params(p)) return NBODY_E_INVAL;
+  if (n_total < 1 || n_total >= ((int64_t)1 << 31) - 1 || n_clusters < 1 || n_clusters > n_total)
+    return NBODY_E_INVAL;
+  if (((uintptr_t)workspace & 255) != 0) return NBODY_E_INVAL;
+  if (cluster_offsets[0] != 0 || cluster_offsets[n_clusters] != n_total) return NBODY_E_INVAL;
+  for (int c = 0; c < n_clusters; ++c) {
+    if (cluster_offsets[c + 1] <= cluster_offsets[c]) return NBODY_E_INVAL;
+    if (!(eps[c] >= 0.0) || !isfinite(eps[c])) return NBODY_E_INVAL;
+  }
+  for (int64_t i = 0; i < n_total; ++i) {
+    if (!isfinite(m[i]) || m[i] < 0.0) return NBODY_E_INVAL;
+    for (int d = 0; d < 3; ++d)
+      if (!isfinite(x[d * n_total + i]) || !isfinite(v[d * n_total + i])) return NBODY_E_INVAL;
+  }
+  const Layout L = make_layout(n_total, n_clusters);
+  if (workspace_bytes < L.total) return NBODY_E_NOMEM;
+
+  nbody_ctx* c = new (std::nothrow) nbody_ctx();
+  if (!c) return NBODY_E_NOMEM;
+  c->L = L;
+  c->p = *p;
+  c->stream = (hipStream_t)hip_stream;
+  c->ws = (unsigned char*)workspace;
+  c->n = n_total;
+  c->nc = n_clusters;
+  c->coff.assign(cluster_offsets, cluster_offsets + n_clusters + 1);
+
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  c->grid = cus * 8;
+  c->target_items = cus * 8;
+
+  // host-side tables: cluster of each particle, selection chunks
+  std::vector<int32_t> cid((size_t)n_total), cl_ch((size_t)n_clusters + 1);
+  std::vector<int32_t> ch_cluster;
+  std::vector<int64_t> ch_begin;
+  for (int cc = 0; cc < n_clusters; ++cc) {
+    cl_ch[cc] = (int32_t)ch_begin.size();
+    for (int64_t i = cluster_offsets[cc]; i < cluster_offsets[cc + 1]; ++i) cid[(size_t)i] = cc;
+    for (int64_t b = cluster_offsets[cc]; b < cluster_offsets[cc + 1]; b += kSelChunk) {
+      ch_cluster.push_back(cc);
+      ch_begin.push_back(b);
+    }
+  }
+  cl_ch[n_clusters] = (int32_t)ch_begin.size();
+  c->nch = (int32_t)ch_begin.size();
+  ch_begin.push_back(n_total);
+
+  DevState& s = c->s;
+  unsigned char* w = c->ws;
+  s.n = n_total;
+  s.nc = n_clusters;
+  s.nch = c->nch;
+  s.coff = (const int64_t*)(w + L.coff);
+  s.eps = (const double*)(w + L.eps);
+  s.cid = (const int32_t*)(w + L.cid);
+  s.ch_cluster = (const int32_t*)(w + L.ch_cluster);
+  s.ch_begin = (const int64_t*)(w + L.ch_begin);
+  s.cl_ch = (const int32_t*)(w + L.cl_ch);
+  s.m = (double*)(w + L.m);
+  s.x = (double*)(w + L.x);
+  s.v = (double*)(w + L.v);
+  s.a = (double*)(w + L.a);
+  s.k = (double*)(w + L.k);
+  s.t = (double*)(w + L.t);
+  s.dt = (double*)(w + L.dt);
+  s.xp = (double*)(w + L.xp);
+  s.vp = (double*)(w + L.vp);
+  s.pot = (double*)(w + L.pot);
+  s.jr = (float*)(w + L.jr);
+  s.tpred = (double*)(w + L.tpred);
+  s.tnow = (double*)(w + L.tnow);
+  s.tsys = (double*)(w + L.tsys);
+  s.inter = (double*)(w + L.inter);
+  s.steps = (int64_t*)(w + L.steps);
+  s.cmin = (double*)(w + L.cmin);
+  s.ccount = (int32_t*)(w + L.ccount);
+  s.act = (int32_t*)(w + L.act);
+  s.aoff = (int64_t*)(w + L.aoff);
+  s.plan = (Plan*)(w + L.plan);
+  s.ctl = (Ctl*)(w + L.ctl);
+  s.part = (double*)(w + L.part);
+  s.rows_cap = L.rows_cap;
+  s.fout = (double*)(w + L.fout);
+  s.status = (int32_t*)(w + L.status);
+
+  c->ctl.vmin[0] = 192;
+  c->ctl.vmin[1] = 48;
+  c->ctl.vmin[2] = 12;
+
+  const size_t N = (size_t)n_total;
+  hipStream_t st = c->stream;
+  bool ok = true;
+  ok = ok && hipMemsetAsync(w, 0, L.total, st) == hipSuccess;
+  ok = ok && hipMemcpyAsync(w + L.coff, cluster_offsets, 8 * ((size_t)n_clusters + 1), hipMemcpyHostToDevice, st) == hipSuccess;
+  ok = ok && hipMemcpyAsync(w + L.eps, eps, 8 * (size_t)n_clusters, hipMemcpyHostToDevice, st) == hipSuccess;
+  ok = ok && hipMemcpyAsync(w + L.cid, cid.data(), 4 * N, hipMemcpyHostToDevice, st) == hipSuccess;
+  ok = ok && hipMemcpyAsync(w + L.ch_cluster, ch_cluster.data(), 4 * ch_cluster.size(), hipMemcpyHostToDevice, st) == hipSuccess;
+  ok = ok && hipMemcpyAsync(w + L.ch_begin, ch_begin.data(), 8 * ch_begin.size(), hipMemcpyHostToDevice, st) == hipSuccess;
+  ok = ok && hipMemcpyAsync(w + L.cl_ch, cl_ch.data(), 4 * cl_ch.size(), hipMemcpyHostToDevice, st) == hipSuccess;
+  ok = ok && hipMemcpyAsync(w + L.m, m, 8 * N, hipMemcpyHostToDevice, st) == hipSuccess;
+  ok = ok && hipMemcpyAsync(w + L.x, x, 24 * N, hipMemcpyHostToDevice, st) == hipSuccess;
+  ok = ok && hipMemcpyAsync(w + L.v, v, 24 * N, hipMemcpyHostToDevice, st) == hipSuccess;
+  ok = ok && hipStreamSynchronize(st) == hipSuccess;
+  if (!ok) {
+    delete c;
+    return NBODY_E_HIP;
+  }
+  nbody_status r = upload_ctl(c);
+  // start-up (Sect. 2.1): a, k of every particle at t = 0, then initial steps
+  if (r == NBODY_OK && launch_predict_all(s, st) != hipSuccess) r = NBODY_E_HIP;  // tpred = 0: x_p = x
+  if (r == NBODY_OK) r = force_all_internal(c, force_mode(c));
+  if (r == NBODY_OK && launch_init_steps(s, st) != hipSuccess) r = NBODY_E_HIP;
+  if (r != NBODY_OK) {
+    delete c;
+    return r;
+  }
+  c->predicted = true;
+  *out = c;
+  return NBODY_OK;
+}
+
+nbody_status nbody_set_params(nbody_ctx* c, const nbody_params* p) {
+  if (!c || !valid_params(p)) return NBODY_E_INVAL;
+  c->p = *p;
+  return upload_ctl(c);
+}
+
+nbody_status nbody_predict(nbody_ctx* c, const double* t_pred) {
+  if (!c) return NBODY_E_INVAL;
+  if (t_pred) {
+    for (int i = 0; i < c->nc; ++i)
+      if (!isfinite(t_pred[i])) return NBODY_E_INVAL;
+    HIP_OK(hipMemcpyAsync(c->s.tpred, t_pred, 8 * (size_t)c->nc, hipMemcpyHostToDevice, c->stream));
+    HIP_OK(hipStreamSynchronize(c->stream));
+  } else {
+    HIP_OK(hipMemcpyAsync(c->s.tpred, c->s.tnow, 8 * (size_t)c->nc, hipMemcpyDeviceToDevice, c->stream));
+  }
+  HIP_OK(launch_predict_all(c->s, c->stream));
+  c->predicted = true;
+  return NBODY_OK;
+}
+
+nbody_status nbody_force(nbody_ctx* c, const int32_t* active_idx, const int64_t* active_offsets, int64_t n_active,
+                         double* acc, double* jerk, double* pot) {
+  if (!c || n_active < 0 || n_active > c->n) return NBODY_E_INVAL;
+  if (n_active == 0) return NBODY_OK;
+  if (!active_idx || !active_offsets || !acc || !jerk) return NBODY_E_INVAL;
+  if (!c->predicted) return NBODY_E_STATE;
+  const DevState& s = c->s;
+  HIP_OK(launch_plan(s, active_offsets, n_active, c->target_items, c->stream));
+  HIP_OK(launch_force(s, force_mode(c), active_idx, c->grid, c->stream));
+  HIP_OK(launch_reduce(s, active_offsets, n_active, acc, jerk, pot, c->stream));
+  return NBODY_OK;
+}
+
+nbody_status nbody_correct(nbody_ctx* c, const int32_t* active_idx, const int64_t* active_offsets, int64_t n_active,
+                           const double* acc, const double* jerk) {
+  if (!c || n_active < 0 || n_active > c->n) return NBODY_E_INVAL;
+  if (n_active == 0) return NBODY_OK;
+  if (!active_idx || !active_offsets || !acc || !jerk) return NBODY_E_INVAL;
+  if (!c->predicted) return NBODY_E_STATE;
+  HIP_OK(launch_correct(c->s, active_idx, active_offsets, n_active, acc, jerk, 0, c->stream));
+  return NBODY_OK;
+}
+
+nbody_status nbody_step(nbody_ctx* c, int32_t n_block_steps, double t_end) {
+  if (!c || n_block_steps < 0 || !(t_end >= 0.0) || !isfinite(t_end)) return NBODY_E_INVAL;
+  if (fmod(t_end, c->p.dt_max) != 0.0) return NBODY_E_INVAL;
+  if (n_block_steps == 0) return NBODY_OK;
+  if (!c->gexec || c->graph_mode != force_mode(c) || c->graph_pot != c->p.compute_pot) {
+    const nbody_status r = build_graph(c);
+    if (r != NBODY_OK) return r;
+  }
+  if (c->ctl.t_end != t_end) {
+    c->ctl.t_end = t_end;
+    HIP_OK(hipMemcpyAsync(&c->s.ctl->t_end, &c->ctl.t_end, sizeof(double), hipMemcpyHostToDevice, c->stream));
+    HIP_OK(hipStreamSynchronize(c->stream));
+  }
+  for (int32_t i = 0; i < n_block_steps; ++i) HIP_OK(hipGraphLaunch(c->gexec, c->stream));
+  c->predicted = true;
+  return NBODY_OK;
+}
+
+nbody_status nbody_sync(nbody_ctx* c) {
+  if (!c) return NBODY_E_INVAL;
+  HIP_OK(hipStreamSynchronize(c->stream));
+  int32_t bits = 0;
+  HIP_OK(hipMemcpy(&bits, c->s.status, sizeof(int32_t), hipMemcpyDeviceToHost));
+  return status_from_bits(bits);
+}
+
+nbody_status nbody_energy(nbody_ctx* c, double* E_host) {
+  if (!c || !E_host) return NBODY_E_INVAL;
+  const DevState& s = c->s;
+  HIP_OK(hipMemcpyAsync(s.tpred, s.tnow, 8 * (size_t)c->nc, hipMemcpyDeviceToDevice, c->stream));
+  HIP_OK(launch_predict_all(s, c->stream));
+  nbody_status r = force_all_internal(c, kF64);
+  if (r != NBODY_OK) return r;
+  double* eout = (double*)(c->ws + c->L.eout);
+  HIP_OK(launch_energy(s, eout, c->stream));
+  HIP_OK(hipMemcpyAsync(E_host, eout, 8 * (size_t)c->nc, hipMemcpyDeviceToHost, c->stream));
+  HIP_OK(hipStreamSynchronize(c->stream));
+  c->predicted = true;
+  return nbody_sync(c);
+}
+
+nbody_status nbody_progress(nbody_ctx* c, double* t_host, int64_t* steps_host, double* inter_host) {
+  if (!c) return NBODY_E_INVAL;
+  const size_t C = (size_t)c->nc;
+  if (t_host) HIP_OK(hipMemcpyAsync(t_host, c->s.tnow, 8 * C, hipMemcpyDeviceToHost, c->stream));
+  if (steps_host) HIP_OK(hipMemcpyAsync(steps_host, c->s.steps, 8 * C, hipMemcpyDeviceToHost, c->stream));
+  if (inter_host) HIP_OK(hipMemcpyAsync(inter_host, c->s.inter, 8 * C, hipMemcpyDeviceToHost, c->stream));
+  HIP_OK(hipStreamSynchronize(c->stream));
+  return NBODY_OK;
+}
+
+// State blob: header {magic, version, n (int64), nc (int32), pad} then
+// coff[nc+1] (int64), eps[nc], m[n], x[3n], v[3n], a[3n], k[3n], t[n], dt[n],
+// tnow[nc], inter[nc] (FP64), steps[nc] (int64).
+nbody_status nbody_state_bytes(const nbody_ctx* c, size_t* bytes) {
+  if (!c || !bytes) return NBODY_E_INVAL;
+  const size_t N = (size_t)c->n, C = (size_t)c->nc;
+  *bytes = 24 + 8 * (C + 1) + 8 * C + 8 * (15 * N) + 8 * 3 * C;
+  return NBODY_OK;
+}
+
+
+nbody_status nbody_get_state(nbody_ctx* c, void* host_buf, size_t bytes) {
+  size_t need = 0;
+  if (!c || !host_buf || nbody_state_bytes(c, &need) != NBODY_OK || bytes < need) return NBODY_E_INVAL;
+  unsigned char* h = (unsigned char*)host_buf;
+  const uint32_t hdr[2] = {kStateMagic, kStateVersion};
+  memcpy(h, hdr, 8);
+  memcpy(h + 8, &c->n, 8);
+  const int32_t nc2[2] = {c->nc, 0};
+  memcpy(h + 16, nc2, 8);
+  size_t o = 24;
+  for (const Part& p : state_parts(c)) {
+    HIP_OK(hipMemcpyAsync(h + o, c->ws + p.off, p.bytes, hipMemcpyDeviceToHost, c->stream));
+    o += p.bytes;
+  }
+  HIP_OK(hipStreamSynchronize(c->stream));
+  return NBODY_OK;
+}
+
+nbody_status nbody_set_state(nbody_ctx* c, const void* host_buf, size_t bytes) {
+  size_t need = 0;
+  if (!c || !host_buf || nbody_state_bytes(c, &need) != NBODY_OK || bytes < need) return NBODY_E_INVAL;
+  const unsigned char* h = (const unsigned char*)host_buf;
+  uint32_t hdr[2];
+  int64_t n;
+  int32_t nc2[2];
+  memcpy(hdr, h, 8);
+  memcpy(&n, h + 8, 8);
+  memcpy(nc2, h + 16, 8);
+  if (hdr[0] != kStateMagic || hdr[1] != kStateVersion || n != c->n || nc2[0] != c->nc) return NBODY_E_INVAL;
+  if (memcmp(h + 24, c->coff.data(), 8 * ((size_t)c->nc + 1)) != 0) return NBODY_E_INVAL;
+  size_t o = 24;
+  for (const Part& p : state_parts(c)) {
+    HIP_OK(hipMemcpyAsync(c->ws + p.off, h + o, p.bytes, hipMemcpyHostToDevice, c->stream));
+    o += p.bytes;
+  }
+  HIP_OK(hipStreamSynchronize(c->stream));
+  // the prediction no longer matches the state
+  HIP_OK(hipMemcpyAsync(c->s.tpred, c->s.tnow, 8 * (size_t)c->nc, hipMemcpyDeviceToDevice, c->stream));
+  HIP_OK(launch_predict_all(c->s, c->stream));
+  c->predicted = true;
+  return NBODY_OK;
+}
+
+nbody_status nbody_get_layout(const nbody_ctx* c, nbody_layout* out) {
+  if (!c || !out) return NBODY_E_INVAL;
+  memset(out, 0, sizeof(*out));
+  out->n_total = c->n;
+  out->n_clusters = c->nc;
+  out->m = c->L.m;
+  out->x = c->L.x;
+  out->v = c->L.v;
+  out->a = c->L.a;
+  out->k = c->L.k;
+  out->t = c->L.t;
+  out->dt = c->L.dt;
+  out->xp = c->L.xp;
+  out->vp = c->L.vp;
+  out->pot = c->L.pot;
+  return NBODY_OK;
+}
+
+nbody_status nbody_get_tuning(const nbody_ctx* c, nbody_tuning* t) {
+  if (!c || !t) return NBODY_E_INVAL;
+  t->target_items = c->target_items;
+  for (int i = 0; i < 3; ++i) t->min_block[i] = c->ctl.vmin[i];
+  t->grid = c->grid;
+  t->mixed_format = c->mixed_mode == kMX64 ? 1 : 0;
+  return NBODY_OK;
+}
+
+nbody_status nbody_set_tuning(nbody_ctx* c, const nbody_tuning* t) {
+  if (!c || !t) return NBODY_E_INVAL;
+  if (t->target_items < 1 || t->grid < 1 || t->grid > (1 << 20)) return NBODY_E_INVAL;
+  if (t->mixed_format != 0 && t->mixed_format != 1) return NBODY_E_INVAL;
+  if (t->min_block[0] < t->min_block[1] || t->min_block[1] < t->min_block[2] || t->min_block[2] < 1)
+    return NBODY_E_INVAL;
+  c->target_items = t->target_items;
+  c->grid = t->grid;
+  c->mixed_mode = t->mixed_format == 1 ? kMX64 : kDS;
+  for (int i = 0; i < 3; ++i) c->ctl.vmin[i] = t->min_block[i];
+  destroy_graph(c);  // the captured step bakes in grid, plan target and format
+  return upload_ctl(c);
+}
+
+nbody_status nbody_destroy(nbody_ctx* c) {
+  if (!c) return NBODY_OK;
+  destroy_graph(c);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  delete c;
+  return NBODY_OK;
+}
+
+const char* nbody_strerror(nbody_status s) {
+  switch (s) {
+    case NBODY_OK: return "ok";
+    case NBODY_E_INVAL: return "invalid argument";
+    case NBODY_E_NOMEM: return "workspace too small or host allocation failed";
+    case NBODY_E_HIP: return "HIP runtime error";
+    case NBODY_E_STATE: return "call out of order";
+    case NBODY_E_DTMIN: return "time step fell below dt_min";
+    case NBODY_E_NONFINITE: return "non-finite value in the state or forces";
+    case NBODY_E_INDEX: return "active index outside its cluster or inconsistent active offsets";
+  }
+  return "unknown status";
+}
+
+}  // extern "C"

@@ -1,0 +1,104 @@
+// Shared device-side definitions of libnbody (gfx950).
+//
+// Everything the kernels read or write lives in the caller-owned workspace;
+// DevState carries the pointers into it.  Vector arrays are
+// structure-of-arrays FP64: component d of particle i is at [d * n + i].
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace nb {
+
+// Device status bits, OR-ed into DevState::status by kernels and mapped to
+// nbody_status on the host (first set bit in this order wins).
+enum : int32_t {
+  ST_INDEX = 1,      // active index outside its cluster / bad active offsets
+  ST_NONFINITE = 2,  // non-finite x, v, a or k, or NaN step criterion
+  ST_DTMIN = 4,      // new step below dt_min
+  ST_STATE = 8,      // corrector asked to step by a non-positive time
+};
+
+// Threads per workgroup of every force launch; the i x j layout of a
+// workgroup is (256 / JL) i-slots times JL j-lanes.
+constexpr int kForceThreads = 256;
+// j-records staged in LDS per tile.
+constexpr int kTile = 256;
+// Partial-row budget: a cluster of N particles may use up to
+// kRowsPerParticle * N + kRowsPerCluster rows of slice partials.
+constexpr int64_t kRowsPerParticle = 32;
+constexpr int64_t kRowsPerCluster = 4096;
+// Variants of the i x j layout, indexed by Plan::variant.
+constexpr int kNumVariants = 4;
+__host__ __device__ constexpr int variant_jl(int v) { return v == 0 ? 1 : v == 1 ? 4 : v == 2 ? 16 : 64; }
+__host__ __device__ constexpr int variant_iwg(int v) { return kForceThreads / variant_jl(v); }
+
+// Mixed j-record in HBM: ten FP32 rows of n entries each.
+enum : int { JR_HX = 0, JR_HY, JR_HZ, JR_LX, JR_LY, JR_LZ, JR_VX, JR_VY, JR_VZ, JR_M, JR_ROWS };
+
+// Per-cluster force plan, written by the plan kernel.
+struct Plan {
+  int64_t item_off;   // first work item of this cluster
+  int64_t slot_base;  // first partial row of this cluster
+  int64_t act_off;    // first entry of this cluster in the active list
+  int32_t n_act;      // active particles in this cluster
+  int32_t variant;    // i x j layout (index into variant_jl)
+  int32_t chunks;     // i-chunks of variant_iwg(variant) active particles
+  int32_t slices;     // j-slices
+  int32_t slice_len;  // j per slice (multiple of kTile)
+  int32_t pad;
+};
+
+// Control block read by the captured step graph (so one graph serves any
+// t_end) and per-cluster counters.
+struct Ctl {
+  double t_end;
+  double eta, eta_init, dt_max, dt_min;
+  int32_t compute_pot;
+  int32_t pad;
+  int64_t total_items;  // items of the current plan
+  int64_t total_rows;   // partial rows of the current plan
+  // plan tuning: smallest block size for variants 0, 1, 2 (else variant 3)
+  int32_t vmin[3];
+  int32_t pad2;
+};
+
+struct DevState {
+  int64_t n;          // particles, all clusters
+  int32_t nc;         // clusters
+  int32_t nch;        // selection chunks
+  const int64_t* coff;  // [nc+1] cluster offsets
+  const double* eps;    // [nc] softening
+  const int32_t* cid;   // [n] cluster of each particle
+  const int32_t* ch_cluster;  // [nch] cluster of each selection chunk
+  const int64_t* ch_begin;    // [nch+1] first particle of each chunk (ch_begin[nch] = n)
+  const int32_t* cl_ch;       // [nc+1] first selection chunk of each cluster
+  double* m;
+  double* x;
+  double* v;
+  double* a;
+  double* k;
+  double* t;
+  double* dt;
+  double* xp;
+  double* vp;
+  double* pot;     // [n] potential of the last block (when kept)
+  float* jr;       // [JR_ROWS][n] mixed j-records
+  double* tpred;   // [nc] time of the last prediction
+  double* tnow;    // [nc] time of the last block step
+  double* tsys;    // [nc] next block time (step pipeline)
+  double* inter;   // [nc] pairwise interactions evaluated
+  int64_t* steps;  // [nc] block steps taken
+  double* cmin;    // [nch] chunk minima of t + dt
+  int32_t* ccount; // [nch] active count per chunk
+  int32_t* act;    // [n] active list of the step pipeline
+  int64_t* aoff;   // [nc+1] active offsets of the step pipeline
+  Plan* plan;      // [nc]
+  Ctl* ctl;
+  double* part;    // [7][rows_cap] partial sums
+  int64_t rows_cap;
+  double* fout;    // [7][n] reduced force of internal passes (a, k, pot)
+  int32_t* status;
+};
+
+}  // namespace nb

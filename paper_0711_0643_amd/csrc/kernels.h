@@ -1,0 +1,52 @@
+// Launchers of libnbody's kernels (host side, internal).
+#pragma once
+
+#include "common.h"
+
+namespace nb {
+
+// Pairwise arithmetic modes of the force kernel.
+enum : int { kF64 = 0, kDS = 1, kMX64 = 2 };
+
+// Selection chunk: particles per workgroup of the block-selection kernels.
+constexpr int kSelChunk = 1024;
+constexpr int kSelThreads = 256;
+
+// Force: every work item of the current plan, persistent grid of `grid`
+// workgroups.  act: the active list the plan was made for.
+hipError_t launch_force(const DevState& s, int mode, const int32_t* act, int grid, hipStream_t st);
+
+// Plan the force pass for the active offsets `aoff` (device, nc+1) of an
+// active list of at most n_act_bound entries.  target_items: work items aimed
+// at (fills the GPU); rows of partial sums are bounded by s.rows_cap.
+// count_stats: add the pass to the per-cluster step / interaction counters.
+hipError_t launch_plan(const DevState& s, const int64_t* aoff, int64_t n_act_bound, int64_t target_items,
+                       hipStream_t st, int count_stats = 0);
+
+// Sum the slice partials of every active entry into acc/jerk/pot
+// ([3][n_active], [3][n_active], [n_active] or NULL).
+hipError_t launch_reduce(const DevState& s, const int64_t* aoff, int64_t n_active, double* acc,
+                         double* jerk, double* pot, hipStream_t st);
+
+// Predict every particle of every cluster to s.tpred[c] (FP64 x_p, v_p and
+// the mixed j-records).
+hipError_t launch_predict_all(const DevState& s, hipStream_t st);
+
+// Write the identity active list (act[i] = i, aoff = coff).
+hipError_t launch_identity(const DevState& s, hipStream_t st);
+
+// Start-up: a, k from s.fout, t = 0, dt from the initial rule.
+hipError_t launch_init_steps(const DevState& s, hipStream_t st);
+
+// Corrector + time step for the active list.  If acc/jerk are NULL the
+// slice partials of the current plan are summed instead (step pipeline).
+hipError_t launch_correct(const DevState& s, const int32_t* act, const int64_t* aoff, int64_t n_active_bound,
+                          const double* acc, const double* jerk, int from_plan, hipStream_t st);
+
+// Block selection (three passes) with the predictor fused into the last.
+hipError_t launch_select(const DevState& s, hipStream_t st);
+
+// Per-cluster energy from s.fout's potential row (identity active list).
+hipError_t launch_energy(const DevState& s, double* e_out, hipStream_t st);
+
+}  // namespace nb

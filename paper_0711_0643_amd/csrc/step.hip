@@ -1,0 +1,545 @@
+// Block-step kernels around the force pass (Sect. 2.1 item list):
+// selection of the block, Hermite prediction, planning of the force work,
+// reduction of slice partials, Hermite correction with Aarseth's step
+// criterion and power-of-two quantisation, start-up and energy.
+// All FP64.
+#include <math.h>
+
+#include "common.h"
+#include "kernels.h"
+
+namespace nb {
+
+__device__ __forceinline__ void set_status(const DevState& s, int32_t bit) {
+  __hip_atomic_fetch_or(s.status, bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ---------------------------------------------------------------------------
+// Hermite predictor (Sect. 2.1, predictor equations) for particle i to time
+// tp; also writes the mixed j-record: hi = fl32(x_p), lo = fl32(x_p - hi),
+// FP32 velocity and mass.
+__device__ __forceinline__ void predict_one(const DevState& s, int64_t i, double tp) {
+  const int64_t n = s.n;
+  const double h = tp - s.t[i];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int64_t o = d * n + i;
+    const double x = s.x[o], v = s.v[o], a = s.a[o], k = s.k[o];
+    const double xp = x + h * (v + h * (0.5 * a + h * (k * (1.0 / 6.0))));
+    const double vp = v + h * (a + h * (0.5 * k));
+    s.xp[o] = xp;
+    s.vp[o] = vp;
+    const float hi = (float)xp;
+    s.jr[(JR_HX + d) * n + i] = hi;
+    s.jr[(JR_LX + d) * n + i] = (float)(xp - (double)hi);
+    s.jr[(JR_VX + d) * n + i] = (float)vp;
+  }
+  s.jr[JR_M * n + i] = (float)s.m[i];
+}
+
+__global__ void __launch_bounds__(256) predict_all_kernel(DevState s) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < s.n; i += (int64_t)gridDim.x * blockDim.x)
+    predict_one(s, i, s.tpred[s.cid[i]]);
+}
+
+hipError_t launch_predict_all(const DevState& s, hipStream_t st) {
+  const int64_t g = (s.n + 255) / 256;
+  hipLaunchKernelGGL(predict_all_kernel, dim3((unsigned)(g < 65535 ? g : 65535)), dim3(256), 0, st, s);
+  return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(256) identity_kernel(DevState s) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < s.n; i += (int64_t)gridDim.x * blockDim.x)
+    s.act[i] = (int32_t)i;
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t <= s.nc) s.aoff[t] = s.coff[t];
+}
+
+hipError_t launch_identity(const DevState& s, hipStream_t st) {
+  int64_t g = (s.n + 255) / 256;
+  const int64_t gc = (s.nc + 1 + 255) / 256;
+  if (g < gc) g = gc;
+  hipLaunchKernelGGL(identity_kernel, dim3((unsigned)(g < 65535 ? g : 65535)), dim3(256), 0, st, s);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Work plan of a force pass (one workgroup).  For every cluster: the i x j
+// layout variant from its block size, the number of i-chunks, and the number
+// of j-slices, chosen from the cluster's own block size and particle count
+// only (so a cluster's sums come out bit-identical whether it is planned
+// alone or inside a batch): as many slices as bring the cluster alone to
+// about target_items work items, at most one per LDS tile and at most what
+// the partial-row budget of the cluster allows.  Offsets of items and
+// partial rows are exclusive prefix sums in cluster order.
+__device__ __forceinline__ int64_t wg_exclusive_scan(int64_t v, int64_t* buf, int64_t* total) {
+  const int tid = threadIdx.x;
+  buf[tid] = v;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    const int64_t add = tid >= off ? buf[tid - off] : 0;
+    __syncthreads();
+    buf[tid] += add;
+    __syncthreads();
+  }
+  const int64_t incl = buf[tid];
+  *total = buf[255];
+  __syncthreads();
+  return incl - v;
+}
+
+__device__ __forceinline__ bool bad_range(const int64_t* aoff, const int64_t* coff, int c, int64_t bound) {
+  const int64_t a0 = aoff[c], a1 = aoff[c + 1];
+  return a0 < 0 || a1 < a0 || a1 > bound || a1 - a0 > coff[c + 1] - coff[c];
+}
+
+__global__ void __launch_bounds__(256) plan_kernel(DevState s, const int64_t* __restrict__ aoff,
+                                                   int64_t n_act_bound, int64_t target_items, int count_stats) {
+  __shared__ int64_t sbuf[256];
+  const int tid = threadIdx.x;
+  const int nc = s.nc;
+  const int per = (nc + 255) / 256;
+  const int c0 = tid * per < nc ? tid * per : nc;
+  const int c1 = c0 + per < nc ? c0 + per : nc;
+  const Ctl ctl = *s.ctl;
+
+  bool bad = (tid == 0) && (aoff[0] != 0);
+  for (int c = c0; c < c1; ++c)
+    if (bad_range(aoff, s.coff, c, n_act_bound)) bad = true;
+  if (bad) set_status(s, ST_INDEX);
+
+  int64_t my_items = 0, my_rows = 0;
+  for (int c = c0; c < c1; ++c) {
+    int64_t na = aoff[c + 1] - aoff[c];
+    const int64_t nn = s.coff[c + 1] - s.coff[c];
+    if (bad_range(aoff, s.coff, c, n_act_bound)) na = 0;
+    const int var = na >= ctl.vmin[0] ? 0 : na >= ctl.vmin[1] ? 1 : na >= ctl.vmin[2] ? 2 : 3;
+    const int64_t iwg = variant_iwg(var);
+    const int64_t chunks = (na + iwg - 1) / iwg;
+    int64_t S = 1;
+    if (chunks > 0) {
+      const int64_t smax_tiles = (nn + kTile - 1) / kTile;
+      const int64_t smax_rows = (kRowsPerParticle * nn + kRowsPerCluster) / na;
+      S = (target_items + chunks - 1) / chunks;
+      if (S > smax_tiles) S = smax_tiles;
+      if (S > smax_rows) S = smax_rows;
+      if (S < 1) S = 1;
+    }
+    int64_t slen = (nn + S - 1) / S;
+    slen = (slen + kTile - 1) / kTile * kTile;
+    S = (nn + slen - 1) / slen;
+    Plan& P = s.plan[c];
+    P.n_act = (int32_t)na;
+    P.variant = var;
+    P.chunks = (int32_t)chunks;
+    P.slices = (int32_t)S;
+    P.slice_len = (int32_t)slen;
+    if (count_stats && na > 0) {  // block-step counters (one writer per cluster)
+      s.inter[c] += (double)na * (double)nn;
+      s.steps[c] += 1;
+    }
+    // clamped so that a corrupt offset cannot steer reads out of the list
+    P.act_off = aoff[c] < 0 ? 0 : aoff[c] > n_act_bound ? n_act_bound : aoff[c];
+    my_items += chunks * S;
+    my_rows += S * na;
+  }
+  __syncthreads();
+  int64_t tot_items, tot_rows;
+  int64_t bi = wg_exclusive_scan(my_items, sbuf, &tot_items);
+  int64_t br = wg_exclusive_scan(my_rows, sbuf, &tot_rows);
+  for (int c = c0; c < c1; ++c) {
+    Plan& P = s.plan[c];
+    P.item_off = bi;
+    P.slot_base = br;
+    bi += (int64_t)P.chunks * P.slices;
+    br += (int64_t)P.slices * P.n_act;
+  }
+  if (tid == 0) {
+    if (tot_rows > s.rows_cap) {  // cannot happen with the bounds above; refuse the pass
+      set_status(s, ST_INDEX);
+      tot_items = 0;
+    }
+    s.ctl->total_items = tot_items;
+    s.ctl->total_rows = tot_rows;
+  }
+}
+
+hipError_t launch_plan(const DevState& s, const int64_t* aoff, int64_t n_act_bound, int64_t target_items,
+                       hipStream_t st, int count_stats) {
+  hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(256), 0, st, s, aoff, n_act_bound, target_items, count_stats);
+  return hipGetLastError();
+}
+
+// Cluster owning active entry q: the last cluster whose act_off <= q (empty
+// clusters share act_off with their successor, so the last one wins).
+__device__ __forceinline__ int cluster_of_entry(const Plan* plan, int nc, int64_t q) {
+  int lo = 0, hi = nc - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (plan[mid].act_off <= q) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Sum of the slice partials of entry q (component d), in slice order.
+__device__ __forceinline__ double slice_sum(const DevState& s, const Plan& P, int64_t q, int d) {
+  const int64_t r = P.slot_base + (q - P.act_off);
+  const double* p = s.part + d * s.rows_cap;
+  double acc = 0.0;
+  for (int sl = 0; sl < P.slices; ++sl) acc += p[r + (int64_t)sl * P.n_act];
+  return acc;
+}
+
+__global__ void __launch_bounds__(256) reduce_kernel(DevState s, int64_t n_active, double* acc,
+                                                     double* jerk, double* pot) {
+  const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (q >= n_active) return;
+  const int c = cluster_of_entry(s.plan, s.nc, q);
+  const Plan P = s.plan[c];
+  if (q < P.act_off || q - P.act_off >= P.n_act) {  // n_active disagrees with the active offsets
+    set_status(s, ST_INDEX);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) acc[d * n_active + q] = jerk[d * n_active + q] = 0.0;
+    if (pot) pot[q] = 0.0;
+    return;
+  }
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    acc[d * n_active + q] = slice_sum(s, P, q, d);
+    jerk[d * n_active + q] = slice_sum(s, P, q, 3 + d);
+  }
+  if (pot) pot[q] = slice_sum(s, P, q, 6);
+}
+
+hipError_t launch_reduce(const DevState& s, const int64_t* aoff, int64_t n_active, double* acc,
+                         double* jerk, double* pot, hipStream_t st) {
+  (void)aoff;
+  const int64_t g = (n_active + 255) / 256;
+  hipLaunchKernelGGL(reduce_kernel, dim3((unsigned)g), dim3(256), 0, st, s, n_active, acc, jerk, pot);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Power-of-two steps.
+
+// Largest power of two not above x, for positive finite x (exactly: keep the
+// exponent, clear the mantissa).  Subnormal x gives 0.
+__device__ __forceinline__ double pow2_floor(double x) {
+  return __longlong_as_double(__double_as_longlong(x) & 0x7FF0000000000000LL);
+}
+
+__device__ __forceinline__ double norm3(double a, double b, double c) { return sqrt(a * a + b * b + c * c); }
+
+// New step from the criterion dt_raw (Sect. 2.1 block rule, read as: shrink
+// freely; double at most once, only when t_now is a multiple of 2 dt_old;
+// cap at dt_max; flag steps below dt_min).
+__device__ __forceinline__ double quantize(double dt_raw, double dt_old, double t_now, double dt_max,
+                                           double dt_min, int32_t* st) {
+  if (isnan(dt_raw) || !isfinite(dt_old)) {
+    *st |= ST_NONFINITE;
+    return dt_old;
+  }
+  if (!(dt_raw > 0.0)) {
+    *st |= ST_DTMIN;
+    return dt_old;
+  }
+  double dn = isinf(dt_raw) ? dt_max : pow2_floor(dt_raw);
+  if (dn < dt_old) {
+    // t_now is a multiple of dt_old, hence of any smaller power of two
+  } else {
+    const double q = t_now / (2.0 * dt_old);  // exact: division by a power of two
+    dn = (dn >= 2.0 * dt_old && q == floor(q)) ? 2.0 * dt_old : dt_old;
+  }
+  if (dn > dt_max) dn = dt_max;
+  if (dn < dt_min) *st |= ST_DTMIN;
+  return dn;
+}
+
+__global__ void __launch_bounds__(256) init_steps_kernel(DevState s) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= s.n) return;
+  const int64_t n = s.n;
+  const Ctl ctl = *s.ctl;
+  double a[3], k[3];
+  int32_t st = 0;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    a[d] = s.fout[d * n + i];
+    k[d] = s.fout[(3 + d) * n + i];
+    s.a[d * n + i] = a[d];
+    s.k[d * n + i] = k[d];
+    if (!isfinite(a[d]) || !isfinite(k[d])) st |= ST_NONFINITE;
+  }
+  const double na = norm3(a[0], a[1], a[2]), nk = norm3(k[0], k[1], k[2]);
+  double dt;
+  if (nk == 0.0) {
+    dt = ctl.dt_max;
+  } else {
+    const double raw = ctl.eta_init * na / nk;
+    if (!(raw > 0.0) || !isfinite(raw)) {
+      st |= (raw == 0.0) ? ST_DTMIN : ST_NONFINITE;
+      dt = ctl.dt_min;
+    } else {
+      dt = pow2_floor(raw);
+    }
+  }
+  if (dt > ctl.dt_max) dt = ctl.dt_max;
+  if (dt < ctl.dt_min) st |= ST_DTMIN;
+  s.t[i] = 0.0;
+  s.dt[i] = dt;
+  if (st) set_status(s, st);
+}
+
+hipError_t launch_init_steps(const DevState& s, hipStream_t st) {
+  hipLaunchKernelGGL(init_steps_kernel, dim3((unsigned)((s.n + 255) / 256)), dim3(256), 0, st, s);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Hermite corrector (Sect. 2.1, corrector equations), Aarseth's criterion
+// (Eq. timestep) with the end-of-step quantities, and quantisation.
+// Entry q of the active list advances particle act[q] to tpred of its
+// cluster.
+__global__ void __launch_bounds__(256) correct_kernel(DevState s, const int32_t* __restrict__ act,
+                                                      const int64_t* __restrict__ aoff, int64_t n_bound,
+                                                      const double* __restrict__ acc,
+                                                      const double* __restrict__ jerk, int from_plan) {
+  const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int nc = s.nc;
+  const int64_t n_active = from_plan ? aoff[nc] : n_bound;
+  if (q >= n_active) return;
+  const int64_t n = s.n;
+  const Ctl ctl = *s.ctl;
+  // cluster of entry q: last c with aoff[c] <= q
+  int lo = 0, hi = nc - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (aoff[mid] <= q) lo = mid; else hi = mid - 1;
+  }
+  const int c = lo;
+  if (q >= aoff[nc] || aoff[0] != 0) {  // n_active disagrees with the active offsets
+    set_status(s, ST_INDEX);
+    return;
+  }
+  const int64_t i = act[q];
+  if (i < s.coff[c] || i >= s.coff[c + 1]) {
+    set_status(s, ST_INDEX);
+    return;
+  }
+  double a1[3], k1[3];
+  if (from_plan) {
+    const Plan P = s.plan[c];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      a1[d] = slice_sum(s, P, q, d);
+      k1[d] = slice_sum(s, P, q, 3 + d);
+    }
+    if (ctl.compute_pot) s.pot[i] = slice_sum(s, P, q, 6);
+  } else {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      a1[d] = acc[d * n_bound + q];
+      k1[d] = jerk[d * n_bound + q];
+    }
+  }
+  const double t_new = s.tpred[c];
+  const double h = t_new - s.t[i];
+  int32_t st = 0;
+  if (!(h > 0.0)) {
+    set_status(s, ST_STATE);
+    return;
+  }
+  const double h2 = h * h, h3 = h2 * h, h4 = h3 * h, h5 = h4 * h;
+  double a2[3], a3[3], a2p[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int64_t o = d * n + i;
+    const double a0 = s.a[o], k0 = s.k[o];
+    const double da = a0 - a1[d];
+    a2[d] = -6.0 * da / h2 - (4.0 * k0 + 2.0 * k1[d]) / h;
+    a3[d] = 12.0 * da / h3 + 6.0 * (k0 + k1[d]) / h2;
+    const double xn = s.xp[o] + a2[d] * h4 / 24.0 + a3[d] * h5 / 120.0;
+    const double vn = s.vp[o] + a2[d] * h3 / 6.0 + a3[d] * h4 / 24.0;
+    if (!isfinite(xn) || !isfinite(vn) || !isfinite(a1[d]) || !isfinite(k1[d])) st |= ST_NONFINITE;
+    s.x[o] = xn;
+    s.v[o] = vn;
+    s.a[o] = a1[d];
+    s.k[o] = k1[d];
+    a2p[d] = a2[d] + a3[d] * h;
+  }
+  const double na = norm3(a1[0], a1[1], a1[2]);
+  const double nk = norm3(k1[0], k1[1], k1[2]);
+  const double na2 = norm3(a2p[0], a2p[1], a2p[2]);
+  const double na3 = norm3(a3[0], a3[1], a3[2]);
+  const double den = nk * na3 + na2 * na2;
+  const double raw = den == 0.0 ? INFINITY : sqrt(ctl.eta * (na * na2 + nk * nk) / den);
+  s.dt[i] = quantize(raw, s.dt[i], t_new, ctl.dt_max, ctl.dt_min, &st);
+  s.t[i] = t_new;
+  if (q == aoff[c]) {
+    s.tnow[c] = t_new;
+  }
+  if (st) set_status(s, st);
+}
+
+hipError_t launch_correct(const DevState& s, const int32_t* act, const int64_t* aoff, int64_t n_active_bound,
+                          const double* acc, const double* jerk, int from_plan, hipStream_t st) {
+  const int64_t g = (n_active_bound + 255) / 256;
+  hipLaunchKernelGGL(correct_kernel, dim3((unsigned)g), dim3(256), 0, st, s, act, aoff, n_active_bound, acc,
+                     jerk, from_plan);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Block selection (Sect. 2.1: the particles with the smallest t_i + dt_i).
+// Pass 1: minimum of t + dt per chunk.  Pass 2: block time per cluster and
+// block members per chunk.  Pass 3: ascending compaction into the active
+// list, per-cluster active offsets, and the predictor for every particle of
+// an advancing cluster.  A cluster whose next block time is past t_end
+// contributes no block.
+
+__global__ void __launch_bounds__(kSelThreads) select1_kernel(DevState s) {
+  __shared__ double red[kSelThreads];
+  const int ch = blockIdx.x;
+  const int64_t b = s.ch_begin[ch], e = s.ch_begin[ch + 1];
+  double mn = INFINITY;
+  for (int64_t i = b + threadIdx.x; i < e; i += kSelThreads) {
+    const double ti = s.t[i] + s.dt[i];
+    mn = ti < mn ? ti : mn;
+  }
+  red[threadIdx.x] = mn;
+  __syncthreads();
+  for (int off = kSelThreads / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + off]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) s.cmin[ch] = red[0];
+}
+
+__global__ void __launch_bounds__(kSelThreads) select2_kernel(DevState s) {
+  __shared__ double red[kSelThreads];
+  __shared__ int32_t cnt[kSelThreads];
+  const int ch = blockIdx.x;
+  const int c = s.ch_cluster[ch];
+  const int f0 = s.cl_ch[c], f1 = s.cl_ch[c + 1];
+  double mn = INFINITY;
+  for (int f = f0 + threadIdx.x; f < f1; f += kSelThreads) mn = fmin(mn, s.cmin[f]);
+  red[threadIdx.x] = mn;
+  __syncthreads();
+  for (int off = kSelThreads / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + off]);
+    __syncthreads();
+  }
+  const double tsys = red[0];
+  const bool done = !(tsys <= s.ctl->t_end);
+  int32_t count = 0;
+  if (!done) {
+    const int64_t b = s.ch_begin[ch], e = s.ch_begin[ch + 1];
+    for (int64_t i = b + threadIdx.x; i < e; i += kSelThreads) count += (s.t[i] + s.dt[i] == tsys) ? 1 : 0;
+  }
+  cnt[threadIdx.x] = count;
+  __syncthreads();
+  for (int off = kSelThreads / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off) cnt[threadIdx.x] += cnt[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    s.ccount[ch] = cnt[0];
+    if (ch == f0) s.tsys[c] = done ? -1.0 : tsys;
+  }
+}
+
+__global__ void __launch_bounds__(kSelThreads) select3_kernel(DevState s) {
+  constexpr int PT = kSelChunk / kSelThreads;  // particles per thread
+  __shared__ int32_t sb[kSelThreads];
+  __shared__ int64_t base_sh;
+  const int ch = blockIdx.x;
+  const int c = s.ch_cluster[ch];
+  const int tid = threadIdx.x;
+  // active entries before this chunk (all clusters)
+  int64_t pre = 0;
+  for (int f = tid; f < ch; f += kSelThreads) pre += s.ccount[f];
+  __shared__ int64_t pbuf[kSelThreads];
+  pbuf[tid] = pre;
+  __syncthreads();
+  for (int off = kSelThreads / 2; off > 0; off >>= 1) {
+    if (tid < off) pbuf[tid] += pbuf[tid + off];
+    __syncthreads();
+  }
+  if (tid == 0) base_sh = pbuf[0];
+  __syncthreads();
+  const int64_t base = base_sh;
+  const double tsys = s.tsys[c];
+  const bool advancing = tsys >= 0.0;
+  const int64_t b = s.ch_begin[ch], e = s.ch_begin[ch + 1];
+  const int64_t i0 = b + (int64_t)tid * PT;
+  int32_t flags = 0, mine = 0;
+  if (advancing) {
+#pragma unroll
+    for (int u = 0; u < PT; ++u) {
+      const int64_t i = i0 + u;
+      if (i < e && s.t[i] + s.dt[i] == tsys) {
+        flags |= 1 << u;
+        ++mine;
+      }
+    }
+  }
+  // exclusive scan of per-thread counts (Hillis-Steele)
+  sb[tid] = mine;
+  __syncthreads();
+  for (int off = 1; off < kSelThreads; off <<= 1) {
+    const int32_t add = tid >= off ? sb[tid - off] : 0;
+    __syncthreads();
+    sb[tid] += add;
+    __syncthreads();
+  }
+  int64_t pos = base + sb[tid] - mine;
+#pragma unroll
+  for (int u = 0; u < PT; ++u)
+    if (flags & (1 << u)) s.act[pos++] = (int32_t)(i0 + u);
+  if (tid == 0) {
+    if (ch == s.cl_ch[c]) {
+      s.aoff[c] = base;
+      if (advancing) s.tpred[c] = tsys;
+    }
+    if (ch == s.nch - 1) s.aoff[s.nc] = base + sb[kSelThreads - 1];
+  }
+  if (advancing) {
+    for (int64_t i = b + tid; i < e; i += kSelThreads) predict_one(s, i, tsys);
+  }
+}
+
+hipError_t launch_select(const DevState& s, hipStream_t st) {
+  hipLaunchKernelGGL(select1_kernel, dim3(s.nch), dim3(kSelThreads), 0, st, s);
+  hipLaunchKernelGGL(select2_kernel, dim3(s.nch), dim3(kSelThreads), 0, st, s);
+  hipLaunchKernelGGL(select3_kernel, dim3(s.nch), dim3(kSelThreads), 0, st, s);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Per-cluster softened energy, E = sum m v^2 / 2 + (1/2) sum m phi, from the
+// potential row of s.fout (identity active list).  Fixed-order sums.
+__global__ void __launch_bounds__(256) energy_kernel(DevState s, double* e_out) {
+  __shared__ double red[256];
+  const int c = blockIdx.x;
+  const int64_t n = s.n;
+  const int64_t b = s.coff[c], e = s.coff[c + 1];
+  double acc = 0.0;
+  for (int64_t i = b + threadIdx.x; i < e; i += 256) {
+    const double vx = s.v[i], vy = s.v[n + i], vz = s.v[2 * n + i];
+    acc += 0.5 * s.m[i] * (vx * vx + vy * vy + vz * vz) + 0.5 * s.m[i] * s.fout[6 * n + i];
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) e_out[c] = red[0];
+}
+
+hipError_t launch_energy(const DevState& s, double* e_out, hipStream_t st) {
+  hipLaunchKernelGGL(energy_kernel, dim3(s.nc), dim3(256), 0, st, s, e_out);
+  return hipGetLastError();
+}
+
+}  // namespace nb

@@ -1,0 +1,263 @@
+"""Parity of the HIP force pass with the FP64 oracle (GPU).
+
+Inputs are seeded Plummer spheres (equal masses, eps = 1/N) and random
+systems; the oracle recomputes a, k, phi from the same FP64 predicted state.
+
+Tolerances:
+  FP64 kernel  -- per particle |da|/|a|, |dk|/|k|, |dphi|/|phi| <= 1e-12
+                  (summation order and FMA differ from the oracle's plain
+                  j-ascending loop; 1e-12 leaves room for cancellation).
+  mixed kernel -- acceleration and potential: per particle relative error
+                  <= 1e-6 (the force-error bar); jerk: error measured against
+                  the sum of absolute jerk terms <= 1e-6 (FP32 pair terms
+                  carry ~5 u = 3e-7 each, and the jerk of a few particles
+                  cancels by a factor ~50), and per-particle relative error
+                  <= 1e-6 for every particle whose jerk cancels by less than
+                  a factor 10.
+"""
+import numpy as np
+import pytest
+
+import icgen
+import oracle
+from tests.gpu_util import banner, normwise_err, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+def _sim(m, x, v, eps, precision, coff=None, **kw):
+    import paper_0711_0643_amd as nb
+
+    return nb.Sim(m, x, v, eps, cluster_offsets=coff, precision=precision, **kw)
+
+
+def _gpu_force(sim, act, aoff=None, pot=True):
+    import torch
+
+    acc, jerk, ph = sim.force(act, aoff, pot=pot)
+    torch.cuda.synchronize()
+    assert sim.status() == 0
+    return acc.cpu().numpy(), jerk.cpu().numpy(), (ph.cpu().numpy() if ph is not None else None)
+
+
+def _check_fp64(got, ref):
+    a, k, p = got
+    ra, rk, rp = ref
+    assert rel_err(a, ra).max() <= 1e-12, rel_err(a, ra).max()
+    assert rel_err(k, rk).max() <= 1e-12, rel_err(k, rk).max()
+    if p is not None:
+        assert rel_err(p, rp).max() <= 1e-12, rel_err(p, rp).max()
+
+
+def _check_mixed(got, ref, absum):
+    a, k, p = got
+    ra, rk, rp = ref
+    ea = rel_err(a, ra)
+    assert ea.max() <= 1e-6, ea.max()
+    ek_norm = normwise_err(k, rk, absum[1])
+    assert ek_norm.max() <= 1e-6, ek_norm.max()
+    kappa_k = absum[1] / np.maximum(np.linalg.norm(rk, axis=0), 1e-300)
+    ek = rel_err(k, rk)
+    assert np.all(ek[kappa_k <= 10] <= 1e-6), ek[kappa_k <= 10].max()
+    if p is not None:
+        assert rel_err(p, rp).max() <= 1e-6, rel_err(p, rp).max()
+
+
+SIZES = [(3, [1, 3]), (64, [1, 7, 40, 64]), (1000, [1, 13, 100, 256, 1000]), (3000, [50, 700, 3000])]
+
+
+@pytest.mark.parametrize("n,acts", SIZES, ids=[f"N{n}" for n, _ in SIZES])
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
+def test_force_plummer_matches_oracle(n, acts, precision):
+    m, x, v = icgen.plummer(n, 100 + n)
+    eps = 1.0 / n
+    banner(f"force plummer N={n} precision={precision}")
+    sim = _sim(m, x, v, eps, precision)
+    for na in acts:
+        act = icgen.active_subset(n, na, seed=7)
+        banner(f"  n_act={na}")
+        got = _gpu_force(sim, act)
+        ref = oracle.force(m, x, v, eps, act)
+        if precision == 0:
+            _check_fp64(got, ref)
+        else:
+            _check_mixed(got, ref, oracle.force_abs(m, x, v, eps, act))
+    sim.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
+def test_force_without_softening(precision):
+    """eps = 0: the self pair must be dropped exactly (masked tiles)."""
+    rng = np.random.default_rng(5)
+    n = 700
+    m = rng.random(n) + 0.5
+    m /= m.sum()
+    x = rng.standard_normal((3, n))
+    v = rng.standard_normal((3, n)) * 0.3
+    banner(f"force eps=0 N={n} precision={precision}")
+    sim = _sim(m, x, v, 0.0, precision)
+    act = icgen.active_subset(n, 333, seed=3)
+    got = _gpu_force(sim, act)
+    ref = oracle.force(m, x, v, 0.0, act)
+    if precision == 0:
+        _check_fp64(got, ref)
+    else:
+        _check_mixed(got, ref, oracle.force_abs(m, x, v, 0.0, act))
+    sim.close()
+
+
+def test_two_body_closed_form_on_gpu():
+    m = np.array([0.25, 0.75])
+    x = np.array([[0.0, 1.5], [0.0, 0.0], [0.0, 0.0]])
+    v = np.zeros((3, 2))
+    banner("two body fp64")
+    sim = _sim(m, x, v, 0.0, 0)
+    a, k, p = _gpu_force(sim, np.array([0, 1], dtype=np.int32))
+    assert abs(a[0, 0] - 0.75 / 1.5**2) < 1e-16 and abs(a[0, 1] + 0.25 / 1.5**2) < 1e-16
+    assert abs(p[0] + 0.75 / 1.5) < 1e-16
+    assert np.all(k == 0)
+    sim.close()
+
+
+def test_single_particle_cluster_has_no_force():
+    banner("single particle")
+    sim = _sim(np.array([1.0]), np.zeros((3, 1)), np.ones((3, 1)), 0.01, 0)
+    a, k, p = _gpu_force(sim, np.array([0], dtype=np.int32))
+    assert np.all(a == 0) and np.all(k == 0) and np.all(p == 0)
+    sim.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
+def test_clusters_are_independent(precision):
+    """Several clusters in one pass: each matches the oracle run on that
+    cluster alone, including an empty block in one cluster."""
+    m, x, v, coff, eps = icgen.ensemble(5, 4, 256, 1500)
+    banner(f"ensemble of 5 precision={precision}")
+    sim = _sim(m, x, v, eps, precision, coff=coff)
+    acts, aoff = [], [0]
+    picks = [37, 0, 300, 1, 256]
+    for c in range(5):
+        nc = int(coff[c + 1] - coff[c])
+        sub = icgen.active_subset(nc, min(picks[c], nc), seed=11 + c) + int(coff[c])
+        acts.append(sub)
+        aoff.append(aoff[-1] + sub.size)
+    act = np.concatenate(acts).astype(np.int32)
+    got = _gpu_force(sim, act, np.array(aoff, dtype=np.int64))
+    for c in range(5):
+        b, e = int(coff[c]), int(coff[c + 1])
+        s = slice(aoff[c], aoff[c + 1])
+        if aoff[c + 1] == aoff[c]:
+            continue
+        loc = acts[c] - b
+        ref = oracle.force(m[b:e], x[:, b:e], v[:, b:e], eps[c], loc)
+        part = (got[0][:, s], got[1][:, s], got[2][s])
+        if precision == 0:
+            _check_fp64(part, ref)
+        else:
+            _check_mixed(part, ref, oracle.force_abs(m[b:e], x[:, b:e], v[:, b:e], eps[c], loc))
+    sim.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
+def test_force_is_deterministic(precision):
+    m, x, v = icgen.plummer(4096, 9)
+    banner(f"determinism precision={precision}")
+    sim = _sim(m, x, v, 1 / 4096, precision)
+    act = icgen.active_subset(4096, 1500)
+    g1 = _gpu_force(sim, act)
+    g2 = _gpu_force(sim, act)
+    for u, w in zip(g1, g2):
+        assert np.array_equal(u, w)
+    sim.close()
+
+
+def test_j_split_changes_only_rounding():
+    """The paper's independence of the processor count: other slicings of j
+    (target_items) agree to FP64 rounding, and the FP64 results stay on the
+    oracle."""
+    n = 5000
+    m, x, v = icgen.plummer(n, 21)
+    banner("j-split invariance")
+    sim = _sim(m, x, v, 1 / n, 0)
+    act = icgen.active_subset(n, 900)
+    ref = oracle.force(m, x, v, 1 / n, act)
+    base = None
+    for target in (1, 7, 64, 2048, 100000):
+        sim.set_tuning(target_items=target)
+        got = _gpu_force(sim, act)
+        _check_fp64(got, ref)
+        if base is None:
+            base = got
+        else:
+            assert rel_err(got[0], base[0]).max() < 1e-13
+    sim.close()
+
+
+def test_layout_variants_agree():
+    """Every i x j layout (1, 4, 16, 64 lanes per i) gives the oracle's sums."""
+    n = 2000
+    m, x, v = icgen.plummer(n, 22)
+    act = icgen.active_subset(n, 300)
+    ref = oracle.force(m, x, v, 1 / n, act)
+    sim = _sim(m, x, v, 1 / n, 0)
+    for mb in ([1, 1, 1], [100000, 1, 1], [100000, 100000, 1], [100000, 100000, 100000]):
+        banner(f"layout min_block={mb}")
+        sim.set_tuning(min_block=mb)
+        _check_fp64(_gpu_force(sim, act), ref)
+    sim.close()
+
+
+def test_empty_block_is_a_no_op():
+    import paper_0711_0643_amd as nb
+
+    m, x, v = icgen.plummer(100, 1)
+    sim = _sim(m, x, v, 0.01, 0)
+    banner("empty block")
+    acc, jerk, _ = sim.force(np.zeros(0, dtype=np.int32))
+    assert acc.shape == (3, 0)
+    assert sim.status() == 0
+    with pytest.raises(nb.NBodyError):
+        sim.force(np.zeros(200, dtype=np.int32))  # more entries than particles
+    sim.close()
+
+
+def test_index_outside_cluster_is_reported():
+    m, x, v, coff, eps = icgen.ensemble(2, 8, 256, 300)
+    banner("bad index")
+    sim = _sim(m, x, v, eps, 0, coff=coff)
+    # entry of cluster 0 pointing into cluster 1
+    act = np.array([0, int(coff[1]) + 3], dtype=np.int32)
+    import torch
+
+    acc, jerk, _ = sim.force(act, np.array([0, 2, 2], dtype=np.int64))
+    torch.cuda.synchronize()
+    assert sim.status() == -7
+    assert np.all(acc.cpu().numpy()[:, 1] == 0)
+    sim.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
+def test_full_size_n65536_sampled(precision):
+    """Plummer N = 65536, eps = 1/N, every particle active (the launch the
+    benchmark times); the oracle checks a sample including the 200 most
+    central particles (strongest cancellation) and 100 random ones."""
+    n = 65536
+    m, x, v = icgen.plummer(n, 3)
+    eps = 1.0 / n
+    banner(f"full size N=65536 precision={precision}")
+    sim = _sim(m, x, v, eps, precision)
+    act = np.arange(n, dtype=np.int32)
+    a, k, p = _gpu_force(sim, act)
+    r = np.sqrt((x * x).sum(0))
+    sample = np.unique(np.concatenate([np.argsort(r)[:200], np.random.default_rng(1).choice(n, 100, replace=False)]))
+    sample = sample.astype(np.int32)
+    ref = oracle.force(m, x, v, eps, sample)
+    got = (a[:, sample], k[:, sample], p[sample])
+    if precision == 0:
+        _check_fp64(got, ref)
+    else:
+        _check_mixed(got, ref, oracle.force_abs(m, x, v, eps, sample))
+    # Newton's third law over the whole system (equal masses): sum a = 0
+    scale = np.abs(a).sum()
+    assert np.abs(a.sum(axis=1)).max() <= (1e-13 if precision == 0 else 1e-6) * scale
+    sim.close()

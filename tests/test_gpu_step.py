@@ -1,0 +1,209 @@
+"""Parity of the HIP predictor, corrector, block selection and block-step
+pipeline with the FP64 oracle (GPU)."""
+import numpy as np
+import pytest
+
+import icgen
+import oracle
+from tests.gpu_util import banner, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+def _sim(m, x, v, eps, precision=0, coff=None, **kw):
+    import paper_0711_0643_amd as nb
+
+    return nb.Sim(m, x, v, eps, cluster_offsets=coff, precision=precision, **kw)
+
+
+def test_startup_matches_oracle():
+    """a, k at t = 0 and the initial power-of-two steps."""
+    n = 1500
+    m, x, v = icgen.plummer(n, 31)
+    eps = 1.0 / n
+    banner("startup")
+    sim = _sim(m, x, v, eps)
+    st = sim.host_state()
+    a, k, _ = oracle.force(m, x, v, eps)
+    assert rel_err(st["a"], a).max() <= 1e-12
+    assert rel_err(st["k"], k).max() <= 1e-12
+    ref_dt = np.array([oracle.initial_dt(0.01, a[:, i], k[:, i], 0.125, 2.0**-40)[0] for i in range(n)])
+    assert np.all(st["t"] == 0.0)
+    # a power-of-two boundary can flip on a last-bit difference; none is expected here
+    assert np.mean(st["dt"] == ref_dt) >= 0.999
+    sim.close()
+
+
+def test_predictor_matches_oracle():
+    n = 2000
+    m, x, v = icgen.plummer(n, 32)
+    banner("predictor")
+    sim = _sim(m, x, v, 1.0 / n)
+    st = sim.host_state()
+    for tp in (0.0, 2.0**-7, 0.1):
+        sim.predict(tp)
+        import torch
+
+        torch.cuda.synchronize()
+        xp, vp = sim.xp.cpu().numpy(), sim.vp.cpu().numpy()
+        rx, rv = oracle.predict(st["x"], st["v"], st["a"], st["k"], st["t"], tp)
+        assert np.max(np.abs(xp - rx)) <= 4e-16 * max(1.0, np.abs(rx).max())
+        assert np.max(np.abs(vp - rv)) <= 4e-16 * max(1.0, np.abs(rv).max())
+        if tp == 0.0:
+            assert np.array_equal(xp, st["x"]) and np.array_equal(vp, st["v"])
+    sim.close()
+
+
+def test_corrector_matches_oracle():
+    """One block step driven through the separate entry points
+    (predict -> force -> correct) against the oracle's corrector, Aarseth
+    criterion and quantisation applied to the same inputs."""
+    import torch
+
+    n = 1024
+    m, x, v = icgen.plummer(n, 33)
+    eps = 1.0 / n
+    banner("corrector")
+    sim = _sim(m, x, v, eps)
+    s0 = sim.host_state()
+    t_sys = float(np.min(s0["t"] + s0["dt"]))
+    block = np.nonzero(s0["t"] + s0["dt"] == t_sys)[0].astype(np.int32)
+    sim.predict(t_sys)
+    acc, jerk, _ = sim.force(block)
+    sim.correct(block, acc, jerk)
+    torch.cuda.synchronize()
+    assert sim.status() == 0
+    s1 = sim.host_state()
+    a1, k1 = acc.cpu().numpy(), jerk.cpu().numpy()
+    xp, vp = oracle.predict(s0["x"], s0["v"], s0["a"], s0["k"], s0["t"], t_sys)
+    same_dt = 0
+    for q, i in enumerate(block):
+        h = t_sys - s0["t"][i]
+        xn, vn, a2, a3 = oracle.correct_one(h, s0["a"][:, i], s0["k"][:, i], a1[:, q], k1[:, q], xp[:, i], vp[:, i])
+        assert rel_err(s1["x"][:, i:i + 1], xn[:, None]).max() <= 1e-14
+        assert rel_err(s1["v"][:, i:i + 1], vn[:, None]).max() <= 1e-14
+        raw = oracle.aarseth_dt(0.01, a1[:, q], k1[:, q], a2, a3, h)
+        dtn, st = oracle.quantize(raw, s0["dt"][i], t_sys, 0.125, 2.0**-40)
+        assert st == 0
+        same_dt += int(dtn == s1["dt"][i])
+        assert s1["t"][i] == t_sys
+        assert np.array_equal(s1["a"][:, i], a1[:, q])
+    assert same_dt >= len(block) - 1
+    # particles outside the block are untouched
+    rest = np.setdiff1d(np.arange(n), block)
+    assert np.array_equal(s1["x"][:, rest], s0["x"][:, rest])
+    assert np.array_equal(s1["dt"][rest], s0["dt"][rest])
+    sim.close()
+
+
+def test_block_steps_follow_oracle_n256():
+    """Plummer N = 256 to t = 1/4 in FP64 through the captured step graph,
+    against the oracle integrator from the same initial conditions: same
+    block structure while the dt decisions agree, and close trajectories."""
+    n = 256
+    m, x, v = icgen.plummer(n, 41)
+    eps = 1.0 / n
+    banner("block steps N=256 fp64")
+    sim = _sim(m, x, v, eps)
+    ref = oracle.Sim(m, x, v, eps)
+    E0 = ref.diagnostics()["E"]
+    steps = 0
+    while True:
+        blk = ref.block_step()
+        sim.step(1, 0.25)
+        steps += 1
+        t_gpu, _, _ = sim.progress()
+        assert t_gpu[0] == ref.time, (steps, t_gpu[0], ref.time)
+        if ref.time >= 0.25:
+            break
+        assert steps < 100000
+    st = sim.host_state()
+    assert sim.status() == 0
+    assert np.all(st["t"] == 0.25)
+    assert np.max(np.abs(st["x"] - ref.x)) < 1e-9
+    assert np.max(np.abs(st["v"] - ref.v)) < 1e-9
+    assert np.mean(st["dt"] == ref.dt) > 0.99
+    E = sim.energy()[0]
+    assert abs(E - ref.diagnostics()["E"]) < 1e-12 * abs(E0)
+    _, gsteps, inter = sim.progress()
+    assert gsteps[0] == steps
+    assert inter[0] == ref.interactions
+    sim.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
+def test_plummer_n1024_to_t1_conserves_energy(precision):
+    """Plummer N = 1024, eps = 1/1024, eta = 0.01, block steps to t = 1:
+    relative energy drift below 1e-5 (FP64 and mixed force)."""
+    n = 1024
+    m, x, v = icgen.plummer(n, 1)
+    eps = 1.0 / 1024
+    banner(f"C1 run to t=1 precision={precision}")
+    sim = _sim(m, x, v, eps, precision=precision)
+    E0 = sim.energy()[0]
+    ref_E0 = oracle.diagnostics(m, x, v, eps)["E"]
+    assert abs(E0 - ref_E0) <= 1e-13 * abs(ref_E0)
+    sim.run(1.0, chunk=256)
+    E1 = sim.energy()[0]
+    assert sim.status() == 0
+    assert abs((E1 - E0) / E0) < 1e-5, (E1 - E0) / E0
+    st = sim.host_state()
+    assert np.all(st["t"] == 1.0)
+    P = st["v"] @ st["m"]
+    assert np.max(np.abs(P)) < 1e-10
+    sim.close()
+
+
+def test_checkpoint_restart_is_bitwise():
+    n = 512
+    m, x, v = icgen.plummer(n, 51)
+    banner("checkpoint")
+    sim = _sim(m, x, v, 1.0 / n)
+    sim.step(40, 0.5)
+    blob = sim.get_state()
+    sim.step(60, 0.5)
+    a = sim.host_state()
+    ta = sim.progress()
+    sim.set_state(blob)
+    sim.step(60, 0.5)
+    b = sim.host_state()
+    tb = sim.progress()
+    for key in a:
+        assert np.array_equal(a[key], b[key]), key
+    for u, w in zip(ta, tb):
+        assert np.array_equal(u, w)
+    sim.close()
+
+
+def test_batched_clusters_match_single_runs():
+    """Four clusters advanced together: every cluster is bit-identical to the
+    same cluster integrated alone (plans depend only on a cluster's own sizes)."""
+    m, x, v, coff, eps = icgen.ensemble(4, 6, 256, 1200)
+    banner("batched vs single")
+    both = _sim(m, x, v, eps, coff=coff)
+    both.run(0.25, chunk=128)
+    sb = both.host_state()
+    tb, nb_steps, _ = both.progress()
+    assert np.all(tb == 0.25)
+    for c in range(4):
+        b, e = int(coff[c]), int(coff[c + 1])
+        one = _sim(m[b:e], x[:, b:e], v[:, b:e], eps[c])
+        one.run(0.25, chunk=128)
+        so = one.host_state()
+        for key in ("x", "v", "a", "k"):
+            assert np.array_equal(sb[key][:, b:e], so[key]), (c, key)
+        assert np.array_equal(sb["dt"][b:e], so["dt"])
+        assert one.progress()[1][0] == nb_steps[c]
+        one.close()
+    both.close()
+
+
+def test_status_reports_step_underflow():
+    """Two bodies 1e-9 apart with no softening need steps far below dt_min = 2^-20."""
+    m = np.array([0.5, 0.5])
+    x = np.array([[0.0, 1e-9], [0.0, 0.0], [0.0, 0.0]])
+    v = np.array([[0.0, 0.0], [-1e-3, 1e-3], [0.0, 0.0]])
+    banner("dt underflow")
+    sim = _sim(m, x, v, 0.0, dt_min=2.0**-20)
+    assert sim.status() == -5
+    sim.close()
