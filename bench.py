@@ -1,0 +1,332 @@
+"""Throughput of the Hermite block-step hot path on one MI355X.
+
+A step is one full block step of the integrator on a Plummer sphere of
+N = 65536 equal masses (eps = 1/N) with every particle in the block: block
+selection, Hermite prediction of all particles, the pairwise acceleration +
+jerk pass of the mixed-precision kernel over all N x N pairs, the reduction
+of slice partials, and the Hermite correction with new time steps.  Shared
+steps (dt = dt_max = 2^-10 for every particle) keep every block full, so a
+step does N^2 interactions.  Inputs are resident in HBM before timing.
+
+Printed: one JSON line with the metric (Ginteractions/s of acc + jerk), the
+roofline of the dominant kernel (the mixed force kernel, timed with HIP
+events around its own launches), the same workload with the FP64 kernel,
+the force error of the mixed kernel against the FP64 kernel, and the FP64
+CPU oracle timed on a bounded sample of the same workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# Algorithmic flops per acc + jerk (+ potential) interaction, counting an
+# FMA as 2 and the reciprocal square root as 1: dr 3, dv 3, R^2 6, rsqrt 1,
+# R^-2 / m R^-1 / m R^-3 3, r.v 5, -3 r.v / R^2 2, a 6, k 12, phi 1.
+FLOPS_PER_INTERACTION = 42
+PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector peak (published; counts packed FP32)
+PEAK_FP64_TFLOPS = 78.6
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--n", type=int, default=65536)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target duration of the CPU sample")
+    ap.add_argument("--kernel-reps", type=int, default=10, help="timed launches of the force kernel alone")
+    ap.add_argument("--no-sweep", action="store_true",
+                    help="full-block runs only (no n_act sweep, no alternative kernels): clean profiles")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run 5 plain device copies of 256 MiB (reference for HBM byte counters)")
+    return ap.parse_args()
+
+
+def calibrate_copy():
+    """Five device-to-device copies of 256 MiB: the hardware byte counters of
+    this known transfer scale the counters read for the force kernel."""
+    import torch
+
+    nbytes = 256 << 20
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "copies": 5}), flush=True)
+
+
+def recorded_traffic():
+    """HBM bytes per launch of the mixed force kernel from the committed
+    rocprofv3 counter summary -- only if force.hip is the source that was
+    profiled (else None)."""
+    import hashlib
+
+    src = os.path.join(ROOT, "paper_0711_0643_amd", "csrc", "force.hip")
+    prof = os.path.join(ROOT, "profiles", "force_mixed_n65536_hbm_counters.txt")
+    try:
+        text = open(prof).read()
+        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    if f"force.hip sha256: {digest}" not in text:
+        return None
+    for line in text.splitlines():
+        if line.startswith("traffic_bytes_per_launch:"):
+            return float(line.split(":", 1)[1])
+    return None
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def time_steps(sim, steps, warmup, dt):
+    import torch
+
+    t_end = (warmup + steps) * dt
+    sim.step(warmup, t_end)
+    sim.sync()
+    torch.cuda.synchronize()
+    t_start, _, _ = sim.progress()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    ev0.record(sim.stream)
+    sim.step(steps, t_end)
+    ev1.record(sim.stream)
+    torch.cuda.synchronize()
+    w1 = time.perf_counter()
+    sim.sync()
+    t_now, steps_done, _ = sim.progress()
+    assert t_now[0] == t_end, (t_now, t_end)
+    return (w1 - w0), ev0.elapsed_time(ev1) / 1e3
+
+
+def kernel_time(sim, act, aoff, reps, warm=3):
+    """Median duration of one force-kernel launch (HIP events around the
+    launch, on the stream it runs on) for the active list `act`, after
+    `warm` untimed calls (the clock settles over the first launches)."""
+    acc, jerk, _ = sim.force(act, aoff)
+    for _ in range(warm):
+        sim.force(act, aoff, out=(acc, jerk, None))
+    sim.sync()
+    sim.profile_force(True)
+    sim.profile_read()
+    times = []
+    for _ in range(reps):
+        sim.force(act, aoff, out=(acc, jerk, None))
+        ms, launches = sim.profile_read()
+        times.append(ms / launches)
+    sim.profile_force(False)
+    sim.sync()
+    return float(np.median(times)) / 1e3, acc, jerk
+
+
+def call_time(sim, act, aoff, reps):
+    """Median duration of a whole nbody_force call (plan + force + reduce),
+    inputs and outputs already on the device."""
+    import torch
+
+    acc, jerk, _ = sim.force(act, aoff)
+    sim.sync()
+    times = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(sim.stream)
+        sim.force(act, aoff, out=(acc, jerk, None))
+        e1.record(sim.stream)
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1))
+    return float(np.median(times)) / 1e3
+
+
+def main():
+    args = parse()
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}), flush=True)
+        sys.exit(2)
+    import torch
+
+    import icgen
+    import paper_0711_0643_amd as nb
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}), flush=True)
+        sys.exit(2)
+    n = args.n
+    eps = 1.0 / n
+    dt = 2.0**-10
+    m, x, v = icgen.plummer(n, 3)
+    log(f"Plummer N={n} eps=1/N, shared steps dt={dt}")
+
+    results = {}
+    # name, precision, tuning overrides, full sweep + steps
+    variants = [("mixed", nb.MIXED, {}, True), ("fp64", nb.FP64, {}, True),
+                ("mixed_no_near_fp64", nb.MIXED, {"near_tau": 0.0}, False),
+                ("mixed_double_single", nb.MIXED, {"mixed_format": 0}, False)]
+    if args.no_sweep:
+        variants = [("mixed", nb.MIXED, {}, False)]
+    for name, prec, tune, full in variants:
+        # eta huge: every step is dt_max, so every block holds all N particles
+        sim = nb.Sim(m, x, v, eps, precision=prec, eta=1e30, eta_init=1e30, dt_max=dt)
+        if tune:
+            sim.set_tuning(**tune)
+        sim.sync()
+        # force kernel alone on the t = 0 state (x_p = x), full block
+        act = torch.arange(n, dtype=torch.int32, device=sim.device)
+        aoff = torch.tensor([0, n], dtype=torch.int64, device=sim.device)
+        kt, acc, jerk = kernel_time(sim, act, aoff, args.kernel_reps, warm=10)
+        res = dict(kernel_s=kt, acc=acc.cpu().numpy(), jerk=jerk.cpu().numpy())
+        if args.no_sweep:
+            wall, evs = time_steps(sim, args.steps, args.warmup, dt)
+            res.update(wall=wall, ev=evs)
+            log(f"{name}: {args.steps} steps {wall * 1e3:.2f} ms wall, force kernel {kt * 1e3:.3f} ms/launch")
+        elif full:
+            sweep = {}
+            for na in (1, 64, 1024, 16384, n):
+                sub = torch.as_tensor(icgen.active_subset(n, na, seed=7), device=sim.device)
+                soff = torch.tensor([0, na], dtype=torch.int64, device=sim.device)
+                kts, _, _ = kernel_time(sim, sub, soff, 5)
+                ct = call_time(sim, sub, soff, 5)
+                sweep[str(na)] = {"kernel_ms": round(kts * 1e3, 4), "call_ms": round(ct * 1e3, 4),
+                                  "Ginteractions_per_s": round(na * float(n) / kts / 1e9, 2)}
+            res["sweep"] = sweep
+            wall, evs = time_steps(sim, args.steps, args.warmup, dt)
+            res.update(wall=wall, ev=evs)
+            log(f"{name}: {args.steps} steps {wall * 1e3:.2f} ms wall ({evs * 1e3:.2f} ms events), "
+                f"force kernel {kt * 1e3:.3f} ms/launch")
+        else:
+            log(f"{name}: force kernel {kt * 1e3:.3f} ms/launch")
+        results[name] = res
+        sim.close()
+        del sim
+
+    inter_step = float(n) * float(n)
+    if args.no_sweep:
+        mx = results["mixed"]
+        print(json.dumps({"metric": "Ginteractions/s acc+jerk at N=65536 (profiling run, no comparisons)",
+                          "value": round(args.steps * inter_step / mx["wall"] / 1e9, 3),
+                          "unit": "Ginteractions/s", "kernel_ms": round(mx["kernel_s"] * 1e3, 4)}), flush=True)
+        return
+    mx, fp = results["mixed"], results["fp64"]
+    value = args.steps * inter_step / mx["wall"] / 1e9
+    # both kernels on the same t = 0 state
+    ea = np.linalg.norm(mx["acc"] - fp["acc"], axis=0) / np.linalg.norm(fp["acc"], axis=0)
+    ek = np.linalg.norm(mx["jerk"] - fp["jerk"], axis=0) / np.linalg.norm(fp["jerk"], axis=0)
+    alt = {}
+    for name in ("mixed_no_near_fp64", "mixed_double_single"):
+        r = results[name]
+        e = np.linalg.norm(r["acc"] - fp["acc"], axis=0) / np.linalg.norm(fp["acc"], axis=0)
+        alt[name] = {"kernel_ms": round(r["kernel_s"] * 1e3, 4),
+                     "Ginteractions_per_s": round(n * float(n) / r["kernel_s"] / 1e9, 2),
+                     "acc_max_rel_vs_fp64": float(e.max()), "n_acc_above_1e-6": int((e > 1e-6).sum())}
+
+    achieved = FLOPS_PER_INTERACTION * inter_step / mx["kernel_s"] / 1e12
+    out = {
+        "metric": "Ginteractions/s acc+jerk at N=65536 (mixed vs FP64, <=1e-6 rel force err)",
+        "value": round(value, 3),
+        "unit": "Ginteractions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(mx["wall"] / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"Plummer sphere N={n}, equal masses, eps=1/N, full-block Hermite block steps "
+                        f"(select, predict, mixed force, reduce, correct), shared dt=2^-10",
+            "n": n,
+            "n_active": n,
+            "precision": "mixed: FP64 position differences rounded to FP32, FP32 pair terms, "
+                         "near pairs (m/R^2 > |a|/4) in FP64, FP64 totals",
+        },
+        "roofline": {
+            "bound": "alu",
+            "achieved": round(achieved, 3),
+            "peak": PEAK_FP32_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+            "traffic": recorded_traffic(),
+            "kernel": "nb::force_kernel<2, false, true> (mixed, FP64 positions, near pairs in FP64)",
+            "flops_per_interaction": FLOPS_PER_INTERACTION,
+            "interactions_per_launch": inter_step,
+            "kernel_ms": round(mx["kernel_s"] * 1e3, 4),
+        },
+        "fp64": {
+            "value": round(args.steps * inter_step / fp["wall"] / 1e9, 3),
+            "ms_per_step": round(fp["wall"] / args.steps * 1e3, 4),
+            "kernel_ms": round(fp["kernel_s"] * 1e3, 4),
+            "kernel_tflops": round(FLOPS_PER_INTERACTION * inter_step / fp["kernel_s"] / 1e12, 3),
+            "frac_of_fp64_peak": round(FLOPS_PER_INTERACTION * inter_step / fp["kernel_s"] / 1e12 / PEAK_FP64_TFLOPS, 4),
+            "force_sweep": fp["sweep"],
+        },
+        "mixed_force_sweep": mx["sweep"],
+        "mixed_alternatives": alt,
+        "mixed_vs_fp64_error": {
+            "acc_max_rel": float(ea.max()),
+            "acc_median_rel": float(np.median(ea)),
+            "jerk_max_rel": float(ek.max()),
+            "jerk_median_rel": float(np.median(ek)),
+            "n_acc_above_1e-6": int((ea > 1e-6).sum()),
+        },
+    }
+
+    if not args.no_cpu:
+        import oracle
+
+        # the oracle on the same t = 0 state, for a sample of active particles
+        # sized to take about args.cpu_seconds on the host cores
+        probe = icgen.active_subset(n, 256, seed=7)
+        t0 = time.perf_counter()
+        oracle.force(m, x, v, eps, probe)
+        t1 = time.perf_counter()
+        per_i = (t1 - t0) / probe.size
+        n_s = int(min(n, max(256, args.cpu_seconds / max(per_i, 1e-9))))
+        sample = icgen.active_subset(n, n_s, seed=7)
+        t0 = time.perf_counter()
+        ra, rk, _ = oracle.force(m, x, v, eps, sample)
+        t1 = time.perf_counter()
+        cpu_rate = n_s * float(n) / (t1 - t0) / 1e9
+        out["cpu_baseline"] = {
+            "value": round(cpu_rate, 5),
+            "unit": "Ginteractions/s",
+            "cores": oracle.threads(),
+            "kind": "oracle",
+            "sample": f"FP64 oracle acc+jerk+pot on {n_s} active particles x {n} (same Plummer state), "
+                      f"{t1 - t0:.1f} s",
+        }
+        # both kernels against the oracle on that sample (same t = 0 state)
+        ea_o = np.linalg.norm(mx["acc"][:, sample] - ra, axis=0) / np.linalg.norm(ra, axis=0)
+        ef_o = np.linalg.norm(fp["acc"][:, sample] - ra, axis=0) / np.linalg.norm(ra, axis=0)
+        out["vs_oracle"] = {"mixed_acc_max_rel": float(ea_o.max()), "fp64_acc_max_rel": float(ef_o.max()),
+                            "mixed_n_acc_above_1e-6": int((ea_o > 1e-6).sum()), "sample": int(n_s)}
+        log(f"cpu oracle: {cpu_rate:.4f} Ginteractions/s on {oracle.threads()} threads")
+
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -191,20 +191,43 @@ NBODY_API nbody_status nbody_get_layout(const nbody_ctx *ctx, nbody_layout *out)
  * in the batch); changing them changes force sums at rounding level only.
  *   target_items: work items (i-chunk x j-slice) a cluster's force pass is
  *                 split into when it has enough tiles (default: 8 per CU).
- *   min_block: smallest block size that uses the 1-, 4- and 16-lane-per-i
- *              layouts (default 192, 48, 12); smaller blocks use 64 lanes
- *              per i.  Must be non-increasing and >= 1.
+ *   min_block: smallest block size that uses, in order, the layouts with
+ *              two i per lane, one i per lane, 4 lanes per i and 16 lanes
+ *              per i (default 384, 192, 48, 12); smaller blocks use 64
+ *              lanes per i.  Must be non-increasing and >= 1.
  *   grid: persistent workgroups of the force launch (default: 8 per CU).
  *   mixed_format: positions of the mixed kernel as double-single FP32
- *                 pairs (0, default) or FP64 (1). */
+ *                 pairs (0) or FP64 (1, default); either way the difference
+ *                 x_j - x_i is formed exactly enough and rounded to FP32.
+ *   rsq_bias_correct: 1 (default) removes the mean relative error of the
+ *                 hardware FP32 reciprocal square root, measured on the
+ *                 device at nbody_init, from the mixed kernel's sums (each
+ *                 FP32 window is scaled in FP64 by 1 - 3b, potential 1 - b);
+ *                 0 leaves the hardware estimate as is.
+ *   near_tau: in the mixed kernel a pair whose term m_j / R^2 exceeds
+ *                 near_tau * |a_i| (|a_i| from the last step) is evaluated
+ *                 in FP64 (default 0.25; 0 turns this off).  One FP32 term
+ *                 carries a few units of FP32 rounding, which limits the
+ *                 relative force error only when that term is comparable
+ *                 to the whole sum (close neighbours). */
 typedef struct {
     int32_t target_items;
-    int32_t min_block[3];
+    int32_t min_block[4];
     int32_t grid;
     int32_t mixed_format;
+    int32_t rsq_bias_correct;
+    double near_tau;
 } nbody_tuning;
 NBODY_API nbody_status nbody_get_tuning(const nbody_ctx *ctx, nbody_tuning *out);
 NBODY_API nbody_status nbody_set_tuning(nbody_ctx *ctx, const nbody_tuning *t);
+
+/* Kernel timing of the force pass: while enabled, nbody_force brackets its
+ * force-kernel launch with HIP events on the context's stream.
+ * nbody_profile_read waits for the stream and returns the summed kernel
+ * time in milliseconds and the number of timed launches since the last
+ * read (or since enabling), then resets both. */
+NBODY_API nbody_status nbody_profile_force(nbody_ctx *ctx, int32_t enable);
+NBODY_API nbody_status nbody_profile_read(nbody_ctx *ctx, double *ms, int64_t *launches);
 
 /* Frees the host context (never the workspace).  NULL is accepted. */
 NBODY_API nbody_status nbody_destroy(nbody_ctx *ctx);

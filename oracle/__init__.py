@@ -59,6 +59,8 @@ def lib() -> ctypes.CDLL:
             path = _LIB
         L = ctypes.CDLL(str(path))
         i64, f64, p = ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
+        L.oracle_threads.argtypes = []
+        L.oracle_threads.restype = ctypes.c_int
         L.oracle_force.argtypes = [i64, p, p, p, f64, i64, p, p, p, p]
         L.oracle_force.restype = None
         L.oracle_force_sliced.argtypes = [i64, p, p, p, f64, i64, i64, p, p, p, p]
@@ -91,6 +93,11 @@ def lib() -> ctypes.CDLL:
         L.oracle_diagnostics.restype = None
         _lib = L
     return _lib
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's parallel loops use."""
+    return int(lib().oracle_threads())
 
 
 def _f64(a) -> np.ndarray:

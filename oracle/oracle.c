@@ -33,6 +33,7 @@
  *   - Initial steps: eta_s |a| / |k| rounded down to a power of two.
  */
 #include <math.h>
+#include <omp.h>
 #include <stddef.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -42,6 +43,9 @@
 #define ORACLE_E_DTMIN (-5)
 #define ORACLE_E_NONFINITE (-6)
 #define ORACLE_E_INVAL (-1)
+
+/* Threads the OpenMP loops of this library use. */
+int oracle_threads(void) { return omp_get_max_threads(); }
 
 /* ---------------------------------------------------------------------- */
 /* Pairwise sums (Sect. 2.1, Eq. Force; jerk and potential as read above). */

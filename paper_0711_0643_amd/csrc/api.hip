@@ -5,11 +5,13 @@
 // the context's stream.  nbody_step captures one block step (select ->
 // plan -> force -> correct) into a HIP graph once and replays it.
 #include <math.h>
+#include <stddef.h>
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 
 #include <new>
+#include <utility>
 #include <vector>
 
 #include "common.h"
@@ -107,7 +109,8 @@ struct nbody_ctx {
   int32_t nch = 0;
   int grid = 2048;        // persistent force grid
   int target_items = 2048;  // work items a force pass aims at per cluster
-  int mixed_mode = kDS;   // position format of the mixed kernel
+  int mixed_mode = kMX64; // position format of the mixed kernel
+  int rsq_correct = 1;    // remove the mean bias of v_rsq_f32 in the mixed kernel
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   int graph_mode = -1;    // force mode the graph was captured with
@@ -115,6 +118,9 @@ struct nbody_ctx {
   bool predicted = false;
   std::vector<int64_t> coff;
   Ctl ctl{};
+  bool profile = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_pending;  // recorded, not yet read
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_free;     // reusable event pairs
 };
 
 namespace {
@@ -132,7 +138,8 @@ nbody_status upload_ctl(nbody_ctx* c) {
   c->ctl.dt_max = c->p.dt_max;
   c->ctl.dt_min = c->p.dt_min;
   c->ctl.compute_pot = c->p.compute_pot ? 1 : 0;
-  HIP_OK(hipMemcpyAsync(c->ws + c->L.ctl, &c->ctl, sizeof(Ctl), hipMemcpyHostToDevice, c->stream));
+  // host-owned fields only: the rsq_* fields at the end are written on the device
+  HIP_OK(hipMemcpyAsync(c->ws + c->L.ctl, &c->ctl, offsetof(Ctl, rsq_scale3), hipMemcpyHostToDevice, c->stream));
   HIP_OK(hipStreamSynchronize(c->stream));  // c->ctl is host memory the copy reads
   return NBODY_OK;
 }
@@ -150,7 +157,7 @@ nbody_status force_all_internal(nbody_ctx* c, int mode) {
   const DevState& s = c->s;
   HIP_OK(launch_identity(s, c->stream));
   HIP_OK(launch_plan(s, s.aoff, s.n, c->target_items, c->stream));
-  HIP_OK(launch_force(s, mode, s.act, c->grid, c->stream));
+  HIP_OK(launch_force(s, mode, true, c->ctl.near_tau > 0.0, s.act, c->grid, c->stream));
   HIP_OK(launch_reduce(s, s.aoff, s.n, s.fout, s.fout + 3 * s.n, s.fout + 6 * s.n, c->stream));
   return NBODY_OK;
 }
@@ -171,8 +178,10 @@ nbody_status build_graph(nbody_ctx* c) {
   HIP_OK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed));
   hipError_t e = launch_select(s, c->cap_stream);
   if (e == hipSuccess) e = launch_plan(s, s.aoff, s.n, c->target_items, c->cap_stream, 1);
-  if (e == hipSuccess) e = launch_force(s, mode, s.act, c->grid, c->cap_stream);
-  if (e == hipSuccess) e = launch_correct(s, s.act, s.aoff, s.n, nullptr, nullptr, 1, c->cap_stream);
+  if (e == hipSuccess)
+    e = launch_force(s, mode, c->p.compute_pot != 0, c->ctl.near_tau > 0.0, s.act, c->grid, c->cap_stream);
+  if (e == hipSuccess) e = launch_reduce_step(s, c->p.compute_pot != 0, c->cap_stream);
+  if (e == hipSuccess) e = launch_correct_step(s, c->p.compute_pot != 0, c->cap_stream);
   hipGraph_t g = nullptr;
   const hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
   if (e != hipSuccess || e2 != hipSuccess || !g) {
@@ -316,9 +325,11 @@ nbody_status nbody_init(nbody_ctx** out, int64_t n_total, int32_t n_clusters, co
   s.fout = (double*)(w + L.fout);
   s.status = (int32_t*)(w + L.status);
 
-  c->ctl.vmin[0] = 192;
-  c->ctl.vmin[1] = 48;
-  c->ctl.vmin[2] = 12;
+  c->ctl.vmin[0] = 384;
+  c->ctl.vmin[1] = 192;
+  c->ctl.vmin[2] = 48;
+  c->ctl.vmin[3] = 12;
+  c->ctl.near_tau = 0.25;
 
   const size_t N = (size_t)n_total;
   hipStream_t st = c->stream;
@@ -339,9 +350,12 @@ nbody_status nbody_init(nbody_ctx** out, int64_t n_total, int32_t n_clusters, co
     return NBODY_E_HIP;
   }
   nbody_status r = upload_ctl(c);
+  if (r == NBODY_OK && launch_rsq_bias(s, c->rsq_correct, st) != hipSuccess) r = NBODY_E_HIP;
   // start-up (Sect. 2.1): a, k of every particle at t = 0, then initial steps
   if (r == NBODY_OK && launch_predict_all(s, st) != hipSuccess) r = NBODY_E_HIP;  // tpred = 0: x_p = x
-  if (r == NBODY_OK) r = force_all_internal(c, force_mode(c));
+  // the start-up pass is FP64 in every precision: one N^2 pass, and its |a|
+  // is what the mixed kernel's near-pair test reads at the first step
+  if (r == NBODY_OK) r = force_all_internal(c, kF64);
   if (r == NBODY_OK && launch_init_steps(s, st) != hipSuccess) r = NBODY_E_HIP;
   if (r != NBODY_OK) {
     delete c;
@@ -381,7 +395,22 @@ nbody_status nbody_force(nbody_ctx* c, const int32_t* active_idx, const int64_t*
   if (!c->predicted) return NBODY_E_STATE;
   const DevState& s = c->s;
   HIP_OK(launch_plan(s, active_offsets, n_active, c->target_items, c->stream));
-  HIP_OK(launch_force(s, force_mode(c), active_idx, c->grid, c->stream));
+  std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+  if (c->profile) {
+    if (!c->prof_free.empty()) {
+      ev = c->prof_free.back();
+      c->prof_free.pop_back();
+    } else {
+      HIP_OK(hipEventCreate(&ev.first));
+      HIP_OK(hipEventCreate(&ev.second));
+    }
+    HIP_OK(hipEventRecord(ev.first, c->stream));
+  }
+  HIP_OK(launch_force(s, force_mode(c), pot != nullptr, c->ctl.near_tau > 0.0, active_idx, c->grid, c->stream));
+  if (c->profile) {
+    HIP_OK(hipEventRecord(ev.second, c->stream));
+    c->prof_pending.push_back(ev);
+  }
   HIP_OK(launch_reduce(s, active_offsets, n_active, acc, jerk, pot, c->stream));
   return NBODY_OK;
 }
@@ -392,7 +421,7 @@ nbody_status nbody_correct(nbody_ctx* c, const int32_t* active_idx, const int64_
   if (n_active == 0) return NBODY_OK;
   if (!active_idx || !active_offsets || !acc || !jerk) return NBODY_E_INVAL;
   if (!c->predicted) return NBODY_E_STATE;
-  HIP_OK(launch_correct(c->s, active_idx, active_offsets, n_active, acc, jerk, 0, c->stream));
+  HIP_OK(launch_correct(c->s, active_idx, active_offsets, n_active, acc, jerk, c->stream));
   return NBODY_OK;
 }
 
@@ -522,9 +551,11 @@ nbody_status nbody_get_layout(const nbody_ctx* c, nbody_layout* out) {
 nbody_status nbody_get_tuning(const nbody_ctx* c, nbody_tuning* t) {
   if (!c || !t) return NBODY_E_INVAL;
   t->target_items = c->target_items;
-  for (int i = 0; i < 3; ++i) t->min_block[i] = c->ctl.vmin[i];
+  for (int i = 0; i < kNumVariants - 1; ++i) t->min_block[i] = c->ctl.vmin[i];
   t->grid = c->grid;
   t->mixed_format = c->mixed_mode == kMX64 ? 1 : 0;
+  t->rsq_bias_correct = c->rsq_correct;
+  t->near_tau = c->ctl.near_tau;
   return NBODY_OK;
 }
 
@@ -532,18 +563,54 @@ nbody_status nbody_set_tuning(nbody_ctx* c, const nbody_tuning* t) {
   if (!c || !t) return NBODY_E_INVAL;
   if (t->target_items < 1 || t->grid < 1 || t->grid > (1 << 20)) return NBODY_E_INVAL;
   if (t->mixed_format != 0 && t->mixed_format != 1) return NBODY_E_INVAL;
-  if (t->min_block[0] < t->min_block[1] || t->min_block[1] < t->min_block[2] || t->min_block[2] < 1)
-    return NBODY_E_INVAL;
+  if (t->rsq_bias_correct != 0 && t->rsq_bias_correct != 1) return NBODY_E_INVAL;
+  if (!(t->near_tau >= 0.0) || !isfinite(t->near_tau)) return NBODY_E_INVAL;
+  for (int i = 0; i < kNumVariants - 1; ++i) {
+    if (t->min_block[i] < 1) return NBODY_E_INVAL;
+    if (i > 0 && t->min_block[i - 1] < t->min_block[i]) return NBODY_E_INVAL;
+  }
   c->target_items = t->target_items;
   c->grid = t->grid;
   c->mixed_mode = t->mixed_format == 1 ? kMX64 : kDS;
-  for (int i = 0; i < 3; ++i) c->ctl.vmin[i] = t->min_block[i];
+  const bool recal = c->rsq_correct != t->rsq_bias_correct;
+  c->rsq_correct = t->rsq_bias_correct;
+  c->ctl.near_tau = t->near_tau;
+  for (int i = 0; i < kNumVariants - 1; ++i) c->ctl.vmin[i] = t->min_block[i];
   destroy_graph(c);  // the captured step bakes in grid, plan target and format
-  return upload_ctl(c);
+  const nbody_status r = upload_ctl(c);
+  if (r == NBODY_OK && recal) HIP_OK(launch_rsq_bias(c->s, c->rsq_correct, c->stream));
+  return r;
+}
+
+nbody_status nbody_profile_force(nbody_ctx* c, int32_t enable) {
+  if (!c) return NBODY_E_INVAL;
+  c->profile = enable != 0;
+  return NBODY_OK;
+}
+
+nbody_status nbody_profile_read(nbody_ctx* c, double* ms, int64_t* launches) {
+  if (!c || !ms || !launches) return NBODY_E_INVAL;
+  HIP_OK(hipStreamSynchronize(c->stream));
+  double total = 0.0;
+  for (auto& ev : c->prof_pending) {
+    float t = 0.f;
+    HIP_OK(hipEventElapsedTime(&t, ev.first, ev.second));
+    total += t;
+    c->prof_free.push_back(ev);
+  }
+  *launches = (int64_t)c->prof_pending.size();
+  *ms = total;
+  c->prof_pending.clear();
+  return NBODY_OK;
 }
 
 nbody_status nbody_destroy(nbody_ctx* c) {
   if (!c) return NBODY_OK;
+  for (auto& ev : c->prof_pending) c->prof_free.push_back(ev);
+  for (auto& ev : c->prof_free) {
+    (void)hipEventDestroy(ev.first);
+    (void)hipEventDestroy(ev.second);
+  }
   destroy_graph(c);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   delete c;

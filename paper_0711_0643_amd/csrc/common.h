@@ -28,10 +28,13 @@ constexpr int kTile = 256;
 // kRowsPerParticle * N + kRowsPerCluster rows of slice partials.
 constexpr int64_t kRowsPerParticle = 32;
 constexpr int64_t kRowsPerCluster = 4096;
-// Variants of the i x j layout, indexed by Plan::variant.
-constexpr int kNumVariants = 4;
-__host__ __device__ constexpr int variant_jl(int v) { return v == 0 ? 1 : v == 1 ? 4 : v == 2 ? 16 : 64; }
-__host__ __device__ constexpr int variant_iwg(int v) { return kForceThreads / variant_jl(v); }
+// Variants of the i x j layout, indexed by Plan::variant: lanes per i (JL)
+// and i per lane (IPT).  v0: 1 lane, 2 i; v1: 1 lane, 1 i; v2: 4 lanes;
+// v3: 16 lanes; v4: 64 lanes.
+constexpr int kNumVariants = 5;
+__host__ __device__ constexpr int variant_jl(int v) { return v <= 1 ? 1 : v == 2 ? 4 : v == 3 ? 16 : 64; }
+__host__ __device__ constexpr int variant_ipt(int v) { return v == 0 ? 2 : 1; }
+__host__ __device__ constexpr int variant_iwg(int v) { return kForceThreads / variant_jl(v) * variant_ipt(v); }
 
 // Mixed j-record in HBM: ten FP32 rows of n entries each.
 enum : int { JR_HX = 0, JR_HY, JR_HZ, JR_LX, JR_LY, JR_LZ, JR_VX, JR_VY, JR_VZ, JR_M, JR_ROWS };
@@ -46,7 +49,8 @@ struct Plan {
   int32_t chunks;     // i-chunks of variant_iwg(variant) active particles
   int32_t slices;     // j-slices
   int32_t slice_len;  // j per slice (multiple of kTile)
-  int32_t pad;
+  int32_t red_tp;     // reduce: lanes per entry (power of two, <= 256)
+  int64_t red_off;    // reduce: first work unit of this cluster
 };
 
 // Control block read by the captured step graph (so one graph serves any
@@ -58,9 +62,16 @@ struct Ctl {
   int32_t pad;
   int64_t total_items;  // items of the current plan
   int64_t total_rows;   // partial rows of the current plan
-  // plan tuning: smallest block size for variants 0, 1, 2 (else variant 3)
-  int32_t vmin[3];
-  int32_t pad2;
+  int64_t total_red;    // reduce work units of the current plan
+  // plan tuning: smallest block size for variants 0..3 (else variant 4)
+  int32_t vmin[kNumVariants - 1];
+  // mixed kernel: pairs with m_j / R^2 > near_tau |a_i| are done in FP64
+  double near_tau;
+  // FP64 factors applied to the FP32 windows of the mixed kernel (bias of
+  // the hardware reciprocal square root removed): R^-3 terms, R^-1 terms
+  double rsq_scale3;
+  double rsq_scale1;
+  double rsq_bias;  // measured mean relative error of v_rsq_f32
 };
 
 struct DevState {

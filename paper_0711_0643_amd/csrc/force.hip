@@ -19,6 +19,13 @@
 //   kDS   : positions as FP32 hi/lo pairs, differenced as
 //           (hi_j - hi_i) + (lo_j - lo_i); pair terms in FP32; partial sums
 //           over windows of at most 32 j in FP32, then added to FP64 totals.
+//           The hardware 1/sqrt (v_rsq_f32) is accurate to < 1 ulp but its
+//           error has a small nonzero mean; summed over N terms that mean
+//           does not average out, and where the pair terms cancel (|a| much
+//           smaller than the sum of |terms|) it dominates the error.  The
+//           library measures that mean relative error b once on the device
+//           (rsq_bias_kernel) and the FP64 flush multiplies the window by
+//           (1 - 3b) for the R^-3 terms and (1 - b) for the potential.
 //   kMX64 : as kDS but the position difference is formed in FP64 from the
 //           predicted FP64 positions and rounded once to FP32.
 // The self pair (j == i) and the zero padding of a ragged last tile are
@@ -124,7 +131,7 @@ struct Acc64 { double v[7]; };
 struct Acc32 { float v[7]; };
 
 // One pair interaction in FP64, added straight into the totals.
-template <bool MASK>
+template <bool MASK, bool POT>
 __device__ __forceinline__ void pair_f64(const ModeT<kF64>::I& I, const RecF64& J, double eps2,
                                          bool drop, Acc64& A) {
   const double dx = J.x - I.x, dy = J.y - I.y, dz = J.z - I.z;
@@ -143,82 +150,207 @@ __device__ __forceinline__ void pair_f64(const ModeT<kF64>::I& I, const RecF64& 
   A.v[3] = __builtin_fma(mr3, __builtin_fma(al, dx, dvx), A.v[3]);
   A.v[4] = __builtin_fma(mr3, __builtin_fma(al, dy, dvy), A.v[4]);
   A.v[5] = __builtin_fma(mr3, __builtin_fma(al, dz, dvz), A.v[5]);
-  A.v[6] -= mr;
+  if (POT) A.v[6] -= mr;
 }
 
-// The FP32 part shared by the mixed modes, given the FP32 differences.
-template <bool MASK>
-__device__ __forceinline__ void pair_f32(float dx, float dy, float dz, float dvx, float dvy,
-                                         float dvz, float m, float eps2, bool drop, Acc32& A) {
-  const float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, __builtin_fmaf(dx, dx, eps2)));
-  float rinv = __builtin_amdgcn_rsqf(r2);
-  if (MASK) rinv = drop ? 0.f : rinv;
+// FP32 differences of one pair (mixed modes) and R^2.
+struct Diff32 { float dx, dy, dz, dvx, dvy, dvz, r2; };
+
+template <int MODE>
+__device__ __forceinline__ Diff32 diff32(const typename ModeT<MODE>::I& I, const typename ModeT<MODE>::Rec& J,
+                                         float eps2) {
+  Diff32 d;
+  if constexpr (MODE == kDS) {
+    d.dx = (J.hx - I.hx) + (J.lx - I.lx);
+    d.dy = (J.hy - I.hy) + (J.ly - I.ly);
+    d.dz = (J.hz - I.hz) + (J.lz - I.lz);
+  } else {
+    d.dx = (float)(J.x - I.x);
+    d.dy = (float)(J.y - I.y);
+    d.dz = (float)(J.z - I.z);
+  }
+  d.dvx = J.vx - I.vx;
+  d.dvy = J.vy - I.vy;
+  d.dvz = J.vz - I.vz;
+  d.r2 = __builtin_fmaf(d.dz, d.dz, __builtin_fmaf(d.dy, d.dy, __builtin_fmaf(d.dx, d.dx, eps2)));
+  return d;
+}
+
+// Weight of an FP32 pair in the near-pair scheme: 1 when its term m_j / R^2
+// (= t) is below the per-i threshold g, 0 above it (the pair then goes to
+// FP64).  Branch-free: (g - t) * 2^40 clamped to [0, 1], computed as one FMA
+// from gB = g * 2^40, so the first pass and the FP64 re-scan get the same
+// weight bit for bit; the FP64 pass adds (1 - weight) of the pair, so the
+// split is exact even in the (measure-zero) fractional case.
+constexpr float kNearScale = 1099511627776.0f;  // 2^40
+__device__ __forceinline__ float near_weight(float t, float gB) {
+  return __builtin_amdgcn_fmed3f(__builtin_fmaf(-t, kNearScale, gB), 0.f, 1.f);
+}
+
+// The rest of an FP32 pair, accumulated into the FP32 window.  ZERO: drop
+// the pair when `drop` is set.  NEAR: scale it by its near-pair weight and
+// keep the smallest weight of the window in *wmin.
+template <bool ZERO, bool POT, bool NEAR>
+__device__ __forceinline__ void finish_f32(const Diff32& d, float m, bool drop, float gB, float* wmin, Acc32& A) {
+  float rinv = __builtin_amdgcn_rsqf(d.r2);
+  if (ZERO) rinv = drop ? 0.f : rinv;
   const float rinv2 = rinv * rinv;
-  const float mr = m * rinv;
-  const float mr3 = mr * rinv2;
-  const float rv = __builtin_fmaf(dz, dvz, __builtin_fmaf(dy, dvy, dx * dvx));
+  float mr, mr3;
+  if (NEAR) {
+    const float t = m * rinv2;  // m_j / R^2
+    const float w = near_weight(t, gB);
+    *wmin = fminf(*wmin, w);
+    const float tw = t * w;
+    mr3 = tw * rinv;
+    mr = POT ? m * rinv * w : 0.f;
+  } else {
+    mr = m * rinv;
+    mr3 = mr * rinv2;
+  }
+  const float rv = __builtin_fmaf(d.dz, d.dvz, __builtin_fmaf(d.dy, d.dvy, d.dx * d.dvx));
   const float al = (-3.f * rinv2) * rv;
-  A.v[0] = __builtin_fmaf(mr3, dx, A.v[0]);
-  A.v[1] = __builtin_fmaf(mr3, dy, A.v[1]);
-  A.v[2] = __builtin_fmaf(mr3, dz, A.v[2]);
-  A.v[3] = __builtin_fmaf(mr3, __builtin_fmaf(al, dx, dvx), A.v[3]);
-  A.v[4] = __builtin_fmaf(mr3, __builtin_fmaf(al, dy, dvy), A.v[4]);
-  A.v[5] = __builtin_fmaf(mr3, __builtin_fmaf(al, dz, dvz), A.v[5]);
-  A.v[6] -= mr;
+  A.v[0] = __builtin_fmaf(mr3, d.dx, A.v[0]);
+  A.v[1] = __builtin_fmaf(mr3, d.dy, A.v[1]);
+  A.v[2] = __builtin_fmaf(mr3, d.dz, A.v[2]);
+  A.v[3] = __builtin_fmaf(mr3, __builtin_fmaf(al, d.dx, d.dvx), A.v[3]);
+  A.v[4] = __builtin_fmaf(mr3, __builtin_fmaf(al, d.dy, d.dvy), A.v[4]);
+  A.v[5] = __builtin_fmaf(mr3, __builtin_fmaf(al, d.dz, d.dvz), A.v[5]);
+  if (POT) A.v[6] -= mr;
 }
 
-template <bool MASK>
-__device__ __forceinline__ void pair_ds(const ModeT<kDS>::I& I, const RecDS& J, float eps2, bool drop,
-                                        Acc32& A) {
-  const float dx = (J.hx - I.hx) + (J.lx - I.lx);
-  const float dy = (J.hy - I.hy) + (J.ly - I.ly);
-  const float dz = (J.hz - I.hz) + (J.lz - I.lz);
-  pair_f32<MASK>(dx, dy, dz, J.vx - I.vx, J.vy - I.vy, J.vz - I.vz, J.m, eps2, drop, A);
+// Near-pair weight of a pair recomputed for the FP64 re-scan, with exactly
+// the operations of the first pass.
+__device__ __forceinline__ float near_weight_again(const Diff32& d, float m, float gB) {
+  const float rinv = __builtin_amdgcn_rsqf(d.r2);
+  return near_weight(m * (rinv * rinv), gB);
 }
 
-template <bool MASK>
-__device__ __forceinline__ void pair_mx(const ModeT<kMX64>::I& I, const RecMX& J, float eps2, bool drop,
-                                        Acc32& A) {
-  const float dx = (float)(J.x - I.x);
-  const float dy = (float)(J.y - I.y);
-  const float dz = (float)(J.z - I.z);
-  pair_f32<MASK>(dx, dy, dz, J.vx - I.vx, J.vy - I.vy, J.vz - I.vz, J.m, eps2, drop, A);
+// A near pair of a mixed mode evaluated in FP64 from the same record: the
+// double-single position hi + lo is exact in FP64, velocities and mass are
+// the record's FP32 values widened.  Added straight into the FP64 totals.
+template <int MODE, bool POT>
+__device__ __forceinline__ void pair_near64(const typename ModeT<MODE>::I& I, const typename ModeT<MODE>::Rec& J,
+                                            double eps2, double share, Acc64& A) {
+  double dx, dy, dz;
+  if constexpr (MODE == kDS) {
+    dx = ((double)J.hx + (double)J.lx) - ((double)I.hx + (double)I.lx);
+    dy = ((double)J.hy + (double)J.ly) - ((double)I.hy + (double)I.ly);
+    dz = ((double)J.hz + (double)J.lz) - ((double)I.hz + (double)I.lz);
+  } else {
+    dx = J.x - I.x;
+    dy = J.y - I.y;
+    dz = J.z - I.z;
+  }
+  const double dvx = (double)J.vx - (double)I.vx;
+  const double dvy = (double)J.vy - (double)I.vy;
+  const double dvz = (double)J.vz - (double)I.vz;
+  const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, __builtin_fma(dx, dx, eps2)));
+  const double rinv = rsqrt_f64(r2);
+  const double rinv2 = rinv * rinv;
+  const double mr = (double)J.m * rinv;
+  const double mr3 = mr * rinv2;
+  const double rv = __builtin_fma(dz, dvz, __builtin_fma(dy, dvy, dx * dvx));
+  const double al = (-3.0 * rinv2) * rv;
+  A.v[0] = __builtin_fma(mr3, dx, A.v[0]);
+  A.v[1] = __builtin_fma(mr3, dy, A.v[1]);
+  A.v[2] = __builtin_fma(mr3, dz, A.v[2]);
+  A.v[3] = __builtin_fma(mr3, __builtin_fma(al, dx, dvx), A.v[3]);
+  A.v[4] = __builtin_fma(mr3, __builtin_fma(al, dy, dvy), A.v[4]);
+  A.v[5] = __builtin_fma(mr3, __builtin_fma(al, dz, dvz), A.v[5]);
+  if (POT) A.v[6] -= mr;
 }
 
-// Sweep this lane's share of one LDS tile.  jl0: first tile-local j of the
-// lane; PER: j per lane per tile; the global index of tile entry u is
-// tile_j0 + u.  MASK drops the lane's own i and entries at or past j_end.
-template <int MODE, int PER, bool MASK>
+// FP64 re-scan of one FP32 window for one i-particle: every pair whose
+// near-pair weight w is below 1 adds (1 - w) of its FP64 value.  Kept out of
+// line: it runs rarely, and inlined its FP64 temporaries would raise the
+// register count (and lower the occupancy) of the whole force kernel.
+template <int MODE, bool MASK, bool POT>
+__device__ __attribute__((noinline)) Acc64 near_window(const typename ModeT<MODE>::Rec* tile, int jl_first, int count,
+                                                       int64_t tile_j0, int64_t j_end, int64_t i_glob,
+                                                       typename ModeT<MODE>::I I, float gB, bool any, double eps2d,
+                                                       float eps2f) {
+  Acc64 R;
+#pragma unroll
+  for (int d = 0; d < 7; ++d) R.v[d] = 0.0;
+  if (!any) return R;
+  for (int u = 0; u < count; ++u) {
+    const int jl = jl_first + u;
+    const int64_t jg = tile_j0 + jl;
+    const typename ModeT<MODE>::Rec J = tile[jl];
+    const bool drop = MASK && (jg == i_glob || jg >= j_end);
+    if (drop) continue;
+    const float wt = near_weight_again(diff32<MODE>(I, J, eps2f), J.m, gB);
+    if (wt < 1.f) pair_near64<MODE, POT>(I, J, eps2d, 1.0 - (double)wt, R);
+  }
+  return R;
+}
+
+// Sweep this lane's share of one LDS tile for its IPT i-particles.  jl0:
+// first tile-local j of the lane; PER: j per lane per tile; the global index
+// of tile entry u is tile_j0 + u.  Each j-record is read from LDS once and
+// used for all IPT particles.  MASK drops the particle's own j and entries at
+// or past j_end.  NEAR (mixed modes): pairs whose term m_j / R^2 exceeds
+// g = tau |a_i| (|a_i| from the last step) are left out of the FP32 window
+// and, after the window, evaluated in FP64 by a wave-uniform re-scan that
+// runs only when some lane met such a pair.  A single FP32 term carries a
+// few u of error, which limits the relative force only when that term is
+// comparable to the whole sum (close neighbours).
+template <int MODE, int PER, int IPT, bool MASK, bool POT, bool NEAR>
 __device__ __forceinline__ void sweep_tile(const typename ModeT<MODE>::Rec* tile, int jl0,
-                                           int64_t tile_j0, int64_t j_end, int64_t i_glob,
-                                           const typename ModeT<MODE>::I& I, double eps2d, float eps2f,
-                                           Acc64& A) {
+                                           int64_t tile_j0, int64_t j_end, const int64_t* i_glob,
+                                           const typename ModeT<MODE>::I* I, const float* gB, double eps2d,
+                                           float eps2f, double ca, double cp, Acc64* A) {
   if constexpr (MODE == kF64) {
 #pragma unroll 8
     for (int u = 0; u < PER; ++u) {
       const int jl = jl0 + u;
       const int64_t jg = tile_j0 + jl;
-      const bool drop = MASK && (jg == i_glob || jg >= j_end);
-      pair_f64<MASK>(I, tile[jl], eps2d, drop, A);
+      const RecF64 J = tile[jl];
+#pragma unroll
+      for (int p = 0; p < IPT; ++p) {
+        const bool drop = MASK && (jg == i_glob[p] || jg >= j_end);
+        pair_f64<MASK, POT>(I[p], J, eps2d, drop, A[p]);
+      }
     }
   } else {
     constexpr int F = PER < 32 ? PER : 32;  // FP32 window, then flush to FP64
     for (int w = 0; w < PER; w += F) {
-      Acc32 B;
+      Acc32 B[IPT];
+      float wmin = 1.f;  // smallest near-pair weight met by this lane in the window
 #pragma unroll
-      for (int d = 0; d < 7; ++d) B.v[d] = 0.f;
+      for (int p = 0; p < IPT; ++p)
+#pragma unroll
+        for (int d = 0; d < 7; ++d) B[p].v[d] = 0.f;
 #pragma unroll
       for (int u = 0; u < F; ++u) {
         const int jl = jl0 + w + u;
         const int64_t jg = tile_j0 + jl;
-        const bool drop = MASK && (jg == i_glob || jg >= j_end);
-        if constexpr (MODE == kDS)
-          pair_ds<MASK>(I, tile[jl], eps2f, drop, B);
-        else
-          pair_mx<MASK>(I, tile[jl], eps2f, drop, B);
-      }
+        const typename ModeT<MODE>::Rec J = tile[jl];
 #pragma unroll
-      for (int d = 0; d < 7; ++d) A.v[d] += (double)B.v[d];
+        for (int p = 0; p < IPT; ++p) {
+          const Diff32 D = diff32<MODE>(I[p], J, eps2f);
+          const bool drop = MASK && (jg == i_glob[p] || jg >= j_end);
+          finish_f32<MASK, POT, NEAR>(D, J.m, drop, gB[p], &wmin, B[p]);
+        }
+      }
+      // flush: the FP32 window times the factor that removes the mean bias
+      // of the hardware reciprocal square root (ca for terms in R^-3, cp for R^-1)
+#pragma unroll
+      for (int p = 0; p < IPT; ++p) {
+#pragma unroll
+        for (int d = 0; d < 6; ++d) A[p].v[d] = __builtin_fma((double)B[p].v[d], ca, A[p].v[d]);
+        if (POT) A[p].v[6] = __builtin_fma((double)B[p].v[6], cp, A[p].v[6]);
+      }
+      if (NEAR && __any(wmin < 1.f)) {
+        // FP64 re-scan of the window for the pairs left out above (rare)
+#pragma unroll
+        for (int p = 0; p < IPT; ++p) {
+          const Acc64 R = near_window<MODE, MASK, POT>(tile, jl0 + w, F, tile_j0, j_end, i_glob[p], I[p], gB[p],
+                                                       wmin < 1.f, eps2d, eps2f);
+#pragma unroll
+          for (int d = 0; d < 7; ++d) A[p].v[d] += R.v[d];
+        }
+      }
     }
   }
 }
@@ -234,41 +366,67 @@ __device__ __forceinline__ int find_cluster(const Plan* plan, int nc, int64_t it
   return lo;
 }
 
-template <int MODE, int JL>
+// One work item.  Layout: JL lanes per i-slot, IPT i-particles per lane
+// (IPT > 1 only with JL = 1); the chunk holds IWG = IPT * 256 / JL entries of
+// the cluster's active list.
+template <int MODE, int JL, int IPT, bool POT, bool NEAR>
 __device__ void run_item(const DevState& s, const int32_t* __restrict__ act, const Plan& P, int c,
                          int64_t local_item, unsigned char* lds) {
-  constexpr int IWG = kForceThreads / JL;
+  static_assert(JL == 1 || IPT == 1, "several i per lane only with one lane per i");
+  constexpr int SLOTS = kForceThreads / JL;  // i-slots per pass
+  constexpr int IWG = SLOTS * IPT;
   constexpr int PER = kTile / JL;
   using Rec = typename ModeT<MODE>::Rec;
   using IT = typename ModeT<MODE>::I;
   Rec* tile = reinterpret_cast<Rec*>(lds);
 
   const int tid = threadIdx.x;
-  const int il = tid % IWG;
-  const int jl = tid / IWG;
+  const int il = tid % SLOTS;
+  const int jl = tid / SLOTS;
   const int chunk = (int)(local_item / P.slices);
   const int slice = (int)(local_item % P.slices);
   const int64_t c_begin = s.coff[c], c_end = s.coff[c + 1];
-  const int q_local = chunk * IWG + il;  // entry of the cluster's active list
-  const bool listed = q_local < P.n_act;
-  bool valid = listed;
-  int64_t i_glob = c_begin;
-  if (valid) {
-    i_glob = act[P.act_off + q_local];
-    if (i_glob < c_begin || i_glob >= c_end) {
-      __hip_atomic_fetch_or(s.status, (int32_t)ST_INDEX, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      valid = false;
-      i_glob = c_begin;
+
+  int q_local[IPT];
+  bool listed[IPT], valid[IPT];
+  int64_t i_glob[IPT];
+  IT I[IPT];
+  Acc64 A[IPT];
+#pragma unroll
+  for (int p = 0; p < IPT; ++p) {
+    q_local[p] = chunk * IWG + p * SLOTS + il;  // entry of the cluster's active list
+    listed[p] = q_local[p] < P.n_act;
+    valid[p] = listed[p];
+    i_glob[p] = c_begin;
+    if (valid[p]) {
+      i_glob[p] = act[P.act_off + q_local[p]];
+      if (i_glob[p] < c_begin || i_glob[p] >= c_end) {
+        __hip_atomic_fetch_or(s.status, (int32_t)ST_INDEX, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        valid[p] = false;
+        i_glob[p] = c_begin;
+      }
     }
+    I[p] = load_i<MODE>(s, i_glob[p]);
+#pragma unroll
+    for (int d = 0; d < 7; ++d) A[p].v[d] = 0.0;
   }
-  const IT I = load_i<MODE>(s, i_glob);
   const double eps = s.eps[c];
   const double eps2d = eps * eps;
   const float eps2f = (float)eps2d;
-
-  Acc64 A;
+  const double ca = s.ctl->rsq_scale3, cp = s.ctl->rsq_scale1;
+  // near-pair threshold g = tau |a_i| (|a_i| of the last step), scaled by
+  // 2^40 for near_weight; no threshold (infinity) while |a_i| is unknown
+  float g[IPT];
 #pragma unroll
-  for (int d = 0; d < 7; ++d) A.v[d] = 0.0;
+  for (int p = 0; p < IPT; ++p) {
+    g[p] = INFINITY;
+    if (NEAR) {
+      const int64_t n = s.n, i = i_glob[p];
+      const double ax = s.a[i], ay = s.a[n + i], az = s.a[2 * n + i];
+      const double gi = s.ctl->near_tau * sqrt(ax * ax + ay * ay + az * az);
+      if (gi > 0.0 && gi < 1e30) g[p] = (float)gi * kNearScale;
+    }
+  }
 
   const int64_t j_begin = c_begin + (int64_t)slice * P.slice_len;
   int64_t j_end = j_begin + P.slice_len;
@@ -281,39 +439,48 @@ __device__ void run_item(const DevState& s, const int32_t* __restrict__ act, con
       tile[r] = (j < j_end) ? load_rec<MODE>(s, j) : zero_rec<MODE>();
     }
     __syncthreads();
-    const bool mine = valid && i_glob >= j0 && i_glob < j0 + kTile;
+    bool mine = false;
+#pragma unroll
+    for (int p = 0; p < IPT; ++p) mine |= valid[p] && i_glob[p] >= j0 && i_glob[p] < j0 + kTile;
     const bool need_mask = (j0 + kTile > j_end) || __any(mine);
     if (need_mask)
-      sweep_tile<MODE, PER, true>(tile, jl * PER, j0, j_end, i_glob, I, eps2d, eps2f, A);
+      sweep_tile<MODE, PER, IPT, true, POT, NEAR>(tile, jl * PER, j0, j_end, i_glob, I, g, eps2d, eps2f, ca, cp, A);
     else
-      sweep_tile<MODE, PER, false>(tile, jl * PER, j0, j_end, i_glob, I, eps2d, eps2f, A);
+      sweep_tile<MODE, PER, IPT, false, POT, NEAR>(tile, jl * PER, j0, j_end, i_glob, I, g, eps2d, eps2f, ca, cp,
+                                                   A);
   }
 
   const int64_t rows_cap = s.rows_cap;
   const int64_t row0 = P.slot_base + (int64_t)slice * P.n_act;
-  if (!valid) {  // unlisted lane, or an index outside its cluster: contributes zeros
 #pragma unroll
-    for (int d = 0; d < 7; ++d) A.v[d] = 0.0;
+  for (int p = 0; p < IPT; ++p) {
+    if (!valid[p]) {  // unlisted slot, or an index outside its cluster: contributes zeros
+#pragma unroll
+      for (int d = 0; d < 7; ++d) A[p].v[d] = 0.0;
+    }
   }
   if constexpr (JL == 1) {
-    if (listed) {
 #pragma unroll
-      for (int d = 0; d < 7; ++d) s.part[d * rows_cap + row0 + q_local] = A.v[d];
+    for (int p = 0; p < IPT; ++p) {
+      if (listed[p]) {
+#pragma unroll
+        for (int d = 0; d < (POT ? 7 : 6); ++d) s.part[d * rows_cap + row0 + q_local[p]] = A[p].v[d];
+      }
     }
   } else {
     // combine the JL lane partials of each i in ascending lane order
     __syncthreads();
     double* red = reinterpret_cast<double*>(lds);
 #pragma unroll
-    for (int d = 0; d < 7; ++d) red[(d * JL + jl) * IWG + il] = A.v[d];
+    for (int d = 0; d < 7; ++d) red[(d * JL + jl) * SLOTS + il] = A[0].v[d];
     __syncthreads();
-    if (tid < IWG) {
+    if (tid < SLOTS) {
       const int q2 = chunk * IWG + tid;
       if (q2 < P.n_act) {
 #pragma unroll
-        for (int d = 0; d < 7; ++d) {
+        for (int d = 0; d < (POT ? 7 : 6); ++d) {
           double sum = 0.0;
-          for (int l = 0; l < JL; ++l) sum += red[(d * JL + l) * IWG + tid];
+          for (int l = 0; l < JL; ++l) sum += red[(d * JL + l) * SLOTS + tid];
           s.part[d * rows_cap + row0 + q2] = sum;
         }
       }
@@ -321,8 +488,13 @@ __device__ void run_item(const DevState& s, const int32_t* __restrict__ act, con
   }
 }
 
-template <int MODE>
-__global__ void __launch_bounds__(kForceThreads) force_kernel(DevState s, const int32_t* __restrict__ act) {
+// POT: also sum the potential (partial row 6); without it row 6 is not written.
+// NEAR: FP64 evaluation of near pairs in the mixed modes.
+// Occupancy is pinned at 3 waves per SIMD (at most 168 VGPRs): left alone,
+// the near-pair variants grow past that and drop to 2 waves.
+template <int MODE, bool POT, bool NEAR>
+__global__ void __launch_bounds__(kForceThreads) __attribute__((amdgpu_waves_per_eu(3)))
+force_kernel(DevState s, const int32_t* __restrict__ act) {
   __shared__ __attribute__((aligned(16))) unsigned char lds[kLdsBytes];
   const int64_t total = s.ctl->total_items;
   for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
@@ -330,20 +502,37 @@ __global__ void __launch_bounds__(kForceThreads) force_kernel(DevState s, const 
     const Plan P = s.plan[c];
     const int64_t local = item - P.item_off;
     switch (P.variant) {
-      case 0: run_item<MODE, 1>(s, act, P, c, local, lds); break;
-      case 1: run_item<MODE, 4>(s, act, P, c, local, lds); break;
-      case 2: run_item<MODE, 16>(s, act, P, c, local, lds); break;
-      default: run_item<MODE, 64>(s, act, P, c, local, lds); break;
+      case 0: run_item<MODE, 1, 2, POT, NEAR>(s, act, P, c, local, lds); break;
+      case 1: run_item<MODE, 1, 1, POT, NEAR>(s, act, P, c, local, lds); break;
+      case 2: run_item<MODE, 4, 1, POT, NEAR>(s, act, P, c, local, lds); break;
+      case 3: run_item<MODE, 16, 1, POT, NEAR>(s, act, P, c, local, lds); break;
+      default: run_item<MODE, 64, 1, POT, NEAR>(s, act, P, c, local, lds); break;
     }
     __syncthreads();  // LDS is reused by the next item
   }
 }
 
-hipError_t launch_force(const DevState& s, int mode, const int32_t* act, int grid, hipStream_t st) {
+template <int MODE, bool NEAR>
+static void launch_mode(const DevState& s, bool pot, const int32_t* act, int grid, hipStream_t st) {
+  if (pot)
+    hipLaunchKernelGGL((force_kernel<MODE, true, NEAR>), dim3(grid), dim3(kForceThreads), 0, st, s, act);
+  else
+    hipLaunchKernelGGL((force_kernel<MODE, false, NEAR>), dim3(grid), dim3(kForceThreads), 0, st, s, act);
+}
+
+hipError_t launch_force(const DevState& s, int mode, bool pot, bool near, const int32_t* act, int grid,
+                        hipStream_t st) {
   switch (mode) {
-    case kF64: hipLaunchKernelGGL(force_kernel<kF64>, dim3(grid), dim3(kForceThreads), 0, st, s, act); break;
-    case kDS: hipLaunchKernelGGL(force_kernel<kDS>, dim3(grid), dim3(kForceThreads), 0, st, s, act); break;
-    default: hipLaunchKernelGGL(force_kernel<kMX64>, dim3(grid), dim3(kForceThreads), 0, st, s, act); break;
+    case kF64: launch_mode<kF64, false>(s, pot, act, grid, st); break;
+    case kDS:
+      if (near) launch_mode<kDS, true>(s, pot, act, grid, st);
+      else launch_mode<kDS, false>(s, pot, act, grid, st);
+      break;
+    case kMX64:
+      if (near) launch_mode<kMX64, true>(s, pot, act, grid, st);
+      else launch_mode<kMX64, false>(s, pot, act, grid, st);
+      break;
+    default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }

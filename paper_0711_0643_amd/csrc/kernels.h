@@ -13,8 +13,11 @@ constexpr int kSelChunk = 1024;
 constexpr int kSelThreads = 256;
 
 // Force: every work item of the current plan, persistent grid of `grid`
-// workgroups.  act: the active list the plan was made for.
-hipError_t launch_force(const DevState& s, int mode, const int32_t* act, int grid, hipStream_t st);
+// workgroups.  act: the active list the plan was made for.  pot: also sum
+// the potential (partial row 6).  near: mixed modes evaluate pairs with
+// m_j / R^2 > ctl->near_tau |a_i| in FP64.
+hipError_t launch_force(const DevState& s, int mode, bool pot, bool near, const int32_t* act, int grid,
+                        hipStream_t st);
 
 // Plan the force pass for the active offsets `aoff` (device, nc+1) of an
 // active list of at most n_act_bound entries.  target_items: work items aimed
@@ -23,10 +26,17 @@ hipError_t launch_force(const DevState& s, int mode, const int32_t* act, int gri
 hipError_t launch_plan(const DevState& s, const int64_t* aoff, int64_t n_act_bound, int64_t target_items,
                        hipStream_t st, int count_stats = 0);
 
+// Persistent grid of the slice reduction.
+constexpr int kReduceGrid = 2048;
+
 // Sum the slice partials of every active entry into acc/jerk/pot
 // ([3][n_active], [3][n_active], [n_active] or NULL).
 hipError_t launch_reduce(const DevState& s, const int64_t* aoff, int64_t n_active, double* acc,
                          double* jerk, double* pot, hipStream_t st);
+
+// Step pipeline: the same into s.fout (rows a, k, pot of stride n) for the
+// active list s.act / s.aoff built by the selection.
+hipError_t launch_reduce_step(const DevState& s, bool pot, hipStream_t st);
 
 // Predict every particle of every cluster to s.tpred[c] (FP64 x_p, v_p and
 // the mixed j-records).
@@ -38,13 +48,21 @@ hipError_t launch_identity(const DevState& s, hipStream_t st);
 // Start-up: a, k from s.fout, t = 0, dt from the initial rule.
 hipError_t launch_init_steps(const DevState& s, hipStream_t st);
 
-// Corrector + time step for the active list.  If acc/jerk are NULL the
-// slice partials of the current plan are summed instead (step pipeline).
-hipError_t launch_correct(const DevState& s, const int32_t* act, const int64_t* aoff, int64_t n_active_bound,
-                          const double* acc, const double* jerk, int from_plan, hipStream_t st);
+// Corrector + time step for an active list with its acc/jerk ([3][n_active]).
+hipError_t launch_correct(const DevState& s, const int32_t* act, const int64_t* aoff, int64_t n_active,
+                          const double* acc, const double* jerk, hipStream_t st);
+
+// Step pipeline: the corrector for s.act / s.aoff reading a, k (and pot)
+// from s.fout.
+hipError_t launch_correct_step(const DevState& s, bool pot, hipStream_t st);
 
 // Block selection (three passes) with the predictor fused into the last.
 hipError_t launch_select(const DevState& s, hipStream_t st);
+
+// Mean relative error b of the FP32 hardware reciprocal square root over
+// log-uniform arguments in [1, 4); sets ctl->rsq_scale3 = 1 - 3b and
+// ctl->rsq_scale1 = 1 - b (or both to 1 when correct == 0).
+hipError_t launch_rsq_bias(const DevState& s, int correct, hipStream_t st);
 
 // Per-cluster energy from s.fout's potential row (identity active list).
 hipError_t launch_energy(const DevState& s, double* e_out, hipStream_t st);

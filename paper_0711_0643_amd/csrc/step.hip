@@ -108,12 +108,14 @@ __global__ void __launch_bounds__(256) plan_kernel(DevState s, const int64_t* __
     if (bad_range(aoff, s.coff, c, n_act_bound)) bad = true;
   if (bad) set_status(s, ST_INDEX);
 
-  int64_t my_items = 0, my_rows = 0;
+  int64_t my_items = 0, my_rows = 0, my_red = 0;
   for (int c = c0; c < c1; ++c) {
     int64_t na = aoff[c + 1] - aoff[c];
     const int64_t nn = s.coff[c + 1] - s.coff[c];
     if (bad_range(aoff, s.coff, c, n_act_bound)) na = 0;
-    const int var = na >= ctl.vmin[0] ? 0 : na >= ctl.vmin[1] ? 1 : na >= ctl.vmin[2] ? 2 : 3;
+    int var = kNumVariants - 1;
+    for (int vv = kNumVariants - 2; vv >= 0; --vv)
+      if (na >= ctl.vmin[vv]) var = vv;
     const int64_t iwg = variant_iwg(var);
     const int64_t chunks = (na + iwg - 1) / iwg;
     int64_t S = 1;
@@ -134,6 +136,9 @@ __global__ void __launch_bounds__(256) plan_kernel(DevState s, const int64_t* __
     P.chunks = (int32_t)chunks;
     P.slices = (int32_t)S;
     P.slice_len = (int32_t)slen;
+    int tp = 1;
+    while (tp < S && tp < 256) tp <<= 1;
+    P.red_tp = tp;
     if (count_stats && na > 0) {  // block-step counters (one writer per cluster)
       s.inter[c] += (double)na * (double)nn;
       s.steps[c] += 1;
@@ -142,25 +147,31 @@ __global__ void __launch_bounds__(256) plan_kernel(DevState s, const int64_t* __
     P.act_off = aoff[c] < 0 ? 0 : aoff[c] > n_act_bound ? n_act_bound : aoff[c];
     my_items += chunks * S;
     my_rows += S * na;
+    my_red += (na + (256 / tp) - 1) / (256 / tp);
   }
   __syncthreads();
-  int64_t tot_items, tot_rows;
+  int64_t tot_items, tot_rows, tot_red;
   int64_t bi = wg_exclusive_scan(my_items, sbuf, &tot_items);
   int64_t br = wg_exclusive_scan(my_rows, sbuf, &tot_rows);
+  int64_t bu = wg_exclusive_scan(my_red, sbuf, &tot_red);
   for (int c = c0; c < c1; ++c) {
     Plan& P = s.plan[c];
     P.item_off = bi;
     P.slot_base = br;
+    P.red_off = bu;
     bi += (int64_t)P.chunks * P.slices;
     br += (int64_t)P.slices * P.n_act;
+    bu += (P.n_act + (256 / P.red_tp) - 1) / (256 / P.red_tp);
   }
   if (tid == 0) {
     if (tot_rows > s.rows_cap) {  // cannot happen with the bounds above; refuse the pass
       set_status(s, ST_INDEX);
       tot_items = 0;
+      tot_red = 0;
     }
     s.ctl->total_items = tot_items;
     s.ctl->total_rows = tot_rows;
+    s.ctl->total_red = tot_red;
   }
 }
 
@@ -170,52 +181,102 @@ hipError_t launch_plan(const DevState& s, const int64_t* aoff, int64_t n_act_bou
   return hipGetLastError();
 }
 
-// Cluster owning active entry q: the last cluster whose act_off <= q (empty
-// clusters share act_off with their successor, so the last one wins).
-__device__ __forceinline__ int cluster_of_entry(const Plan* plan, int nc, int64_t q) {
+// Sum of the slice partials of every active entry (the across-processor sum
+// of the paper's j-parallel scheme, Sect. 3).  Work unit = 256/TP entries of
+// one cluster, TP = lanes per entry (the cluster's slice count rounded up to a
+// power of two, at most 256).  Lane l adds slices l, l + TP, ... in order;
+// the TP lane sums are then combined by a fixed binary tree in LDS.  TP and
+// the order depend only on the cluster's own plan, so the bits of a cluster
+// do not depend on the rest of the batch.  Output component d of entry q goes
+// to out[d][q * 1 + d_stride...]: acc[d * stride + q], jerk[d * stride + q],
+// pot[q] (pot may be NULL).  Entries at or past the active count are skipped.
+__device__ __forceinline__ int cluster_of_unit(const Plan* plan, int nc, int64_t u) {
   int lo = 0, hi = nc - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (plan[mid].act_off <= q) lo = mid; else hi = mid - 1;
+    if (plan[mid].red_off <= u) lo = mid; else hi = mid - 1;
   }
   return lo;
 }
 
-// Sum of the slice partials of entry q (component d), in slice order.
-__device__ __forceinline__ double slice_sum(const DevState& s, const Plan& P, int64_t q, int d) {
-  const int64_t r = P.slot_base + (q - P.act_off);
-  const double* p = s.part + d * s.rows_cap;
-  double acc = 0.0;
-  for (int sl = 0; sl < P.slices; ++sl) acc += p[r + (int64_t)sl * P.n_act];
-  return acc;
+__global__ void __launch_bounds__(256) reduce_kernel(DevState s, const int64_t* __restrict__ aoff,
+                                                     int64_t n_bound, int n_from_aoff, double* acc, double* jerk,
+                                                     double* pot, int64_t stride) {
+  __shared__ double red[7][256];
+  const int tid = threadIdx.x;
+  const int64_t n_active = n_from_aoff ? aoff[s.nc] : n_bound;
+  const int64_t units = s.ctl->total_red;
+  const int64_t rows_cap = s.rows_cap;
+  for (int64_t u = blockIdx.x; u < units; u += gridDim.x) {
+    const int c = cluster_of_unit(s.plan, s.nc, u);
+    const Plan P = s.plan[c];
+    const int tp = P.red_tp;
+    const int epw = 256 / tp;
+    const int lane = tid % tp;
+    const int64_t e = (u - P.red_off) * epw + tid / tp;  // entry within the cluster
+    const bool live = e < P.n_act;
+    const int64_t q = P.act_off + e;
+    double v[7];
+#pragma unroll
+    for (int d = 0; d < 7; ++d) v[d] = 0.0;
+    if (live) {
+      const int64_t r0 = P.slot_base + e;
+      for (int sl = lane; sl < P.slices; sl += tp) {
+        const int64_t r = r0 + (int64_t)sl * P.n_act;
+#pragma unroll
+        for (int d = 0; d < 6; ++d) v[d] += s.part[d * rows_cap + r];
+        if (pot) v[6] += s.part[6 * rows_cap + r];
+      }
+    }
+#pragma unroll
+    for (int d = 0; d < 7; ++d) red[d][tid] = v[d];
+    __syncthreads();
+    for (int off = tp >> 1; off > 0; off >>= 1) {
+      if (lane < off) {
+#pragma unroll
+        for (int d = 0; d < 7; ++d) red[d][tid] += red[d][tid + off];
+      }
+      __syncthreads();
+    }
+    if (live && lane == 0 && q < n_active) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        acc[d * stride + q] = red[d][tid];
+        jerk[d * stride + q] = red[3 + d][tid];
+      }
+      if (pot) pot[q] = red[6][tid];
+    }
+    __syncthreads();  // red is reused by the next unit
+  }
 }
 
-__global__ void __launch_bounds__(256) reduce_kernel(DevState s, int64_t n_active, double* acc,
-                                                     double* jerk, double* pot) {
+// Entries listed past the clusters' active counts (n_active larger than the
+// active offsets say) get zeros and the index status bit.
+__global__ void __launch_bounds__(256) reduce_tail_kernel(DevState s, const int64_t* __restrict__ aoff,
+                                                          int64_t n_active, double* acc, double* jerk,
+                                                          double* pot) {
   const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (q >= n_active) return;
-  const int c = cluster_of_entry(s.plan, s.nc, q);
-  const Plan P = s.plan[c];
-  if (q < P.act_off || q - P.act_off >= P.n_act) {  // n_active disagrees with the active offsets
-    set_status(s, ST_INDEX);
+  const int64_t listed = aoff[s.nc];
+  if (aoff[0] == 0 && q < listed) return;
+  set_status(s, ST_INDEX);
 #pragma unroll
-    for (int d = 0; d < 3; ++d) acc[d * n_active + q] = jerk[d * n_active + q] = 0.0;
-    if (pot) pot[q] = 0.0;
-    return;
-  }
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    acc[d * n_active + q] = slice_sum(s, P, q, d);
-    jerk[d * n_active + q] = slice_sum(s, P, q, 3 + d);
-  }
-  if (pot) pot[q] = slice_sum(s, P, q, 6);
+  for (int d = 0; d < 3; ++d) acc[d * n_active + q] = jerk[d * n_active + q] = 0.0;
+  if (pot) pot[q] = 0.0;
 }
 
 hipError_t launch_reduce(const DevState& s, const int64_t* aoff, int64_t n_active, double* acc,
                          double* jerk, double* pot, hipStream_t st) {
-  (void)aoff;
   const int64_t g = (n_active + 255) / 256;
-  hipLaunchKernelGGL(reduce_kernel, dim3((unsigned)g), dim3(256), 0, st, s, n_active, acc, jerk, pot);
+  hipLaunchKernelGGL(reduce_tail_kernel, dim3((unsigned)g), dim3(256), 0, st, s, aoff, n_active, acc, jerk, pot);
+  hipLaunchKernelGGL(reduce_kernel, dim3(kReduceGrid), dim3(256), 0, st, s, aoff, n_active, 0, acc, jerk, pot,
+                     n_active);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_step(const DevState& s, bool pot, hipStream_t st) {
+  hipLaunchKernelGGL(reduce_kernel, dim3(kReduceGrid), dim3(256), 0, st, s, s.aoff, s.n, 1, s.fout, s.fout + 3 * s.n,
+                     pot ? s.fout + 6 * s.n : nullptr, s.n);
   return hipGetLastError();
 }
 
@@ -303,10 +364,12 @@ hipError_t launch_init_steps(const DevState& s, hipStream_t st) {
 __global__ void __launch_bounds__(256) correct_kernel(DevState s, const int32_t* __restrict__ act,
                                                       const int64_t* __restrict__ aoff, int64_t n_bound,
                                                       const double* __restrict__ acc,
-                                                      const double* __restrict__ jerk, int from_plan) {
+                                                      const double* __restrict__ jerk,
+                                                      const double* __restrict__ pot, int64_t stride,
+                                                      int n_from_aoff) {
   const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int nc = s.nc;
-  const int64_t n_active = from_plan ? aoff[nc] : n_bound;
+  const int64_t n_active = n_from_aoff ? aoff[nc] : n_bound;
   if (q >= n_active) return;
   const int64_t n = s.n;
   const Ctl ctl = *s.ctl;
@@ -327,21 +390,12 @@ __global__ void __launch_bounds__(256) correct_kernel(DevState s, const int32_t*
     return;
   }
   double a1[3], k1[3];
-  if (from_plan) {
-    const Plan P = s.plan[c];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      a1[d] = slice_sum(s, P, q, d);
-      k1[d] = slice_sum(s, P, q, 3 + d);
-    }
-    if (ctl.compute_pot) s.pot[i] = slice_sum(s, P, q, 6);
-  } else {
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      a1[d] = acc[d * n_bound + q];
-      k1[d] = jerk[d * n_bound + q];
-    }
+  for (int d = 0; d < 3; ++d) {
+    a1[d] = acc[d * stride + q];
+    k1[d] = jerk[d * stride + q];
   }
+  if (pot) s.pot[i] = pot[q];
   const double t_new = s.tpred[c];
   const double h = t_new - s.t[i];
   int32_t st = 0;
@@ -381,11 +435,18 @@ __global__ void __launch_bounds__(256) correct_kernel(DevState s, const int32_t*
   if (st) set_status(s, st);
 }
 
-hipError_t launch_correct(const DevState& s, const int32_t* act, const int64_t* aoff, int64_t n_active_bound,
-                          const double* acc, const double* jerk, int from_plan, hipStream_t st) {
-  const int64_t g = (n_active_bound + 255) / 256;
-  hipLaunchKernelGGL(correct_kernel, dim3((unsigned)g), dim3(256), 0, st, s, act, aoff, n_active_bound, acc,
-                     jerk, from_plan);
+hipError_t launch_correct(const DevState& s, const int32_t* act, const int64_t* aoff, int64_t n_active,
+                          const double* acc, const double* jerk, hipStream_t st) {
+  const int64_t g = (n_active + 255) / 256;
+  hipLaunchKernelGGL(correct_kernel, dim3((unsigned)g), dim3(256), 0, st, s, act, aoff, n_active, acc, jerk,
+                     (const double*)nullptr, n_active, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_correct_step(const DevState& s, bool pot, hipStream_t st) {
+  const int64_t g = (s.n + 255) / 256;
+  hipLaunchKernelGGL(correct_kernel, dim3((unsigned)g), dim3(256), 0, st, s, s.act, s.aoff, s.n, s.fout,
+                     s.fout + 3 * s.n, pot ? s.fout + 6 * s.n : nullptr, s.n, 1);
   return hipGetLastError();
 }
 
@@ -512,6 +573,45 @@ hipError_t launch_select(const DevState& s, hipStream_t st) {
   hipLaunchKernelGGL(select1_kernel, dim3(s.nch), dim3(kSelThreads), 0, st, s);
   hipLaunchKernelGGL(select2_kernel, dim3(s.nch), dim3(kSelThreads), 0, st, s);
   hipLaunchKernelGGL(select3_kernel, dim3(s.nch), dim3(kSelThreads), 0, st, s);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Mean relative error of the FP32 hardware reciprocal square root.  One
+// workgroup evaluates v_rsq_f32 at 65536 arguments spread log-uniformly over
+// [1, 4) (its error pattern repeats every two binades), compares each with
+// 1/sqrt in FP64 (v_rsq_f64 estimate plus a third-order Newton step, exact
+// to FP64 rounding), and averages the relative errors in a fixed order.
+__global__ void __launch_bounds__(256) rsq_bias_kernel(Ctl* ctl, int correct) {
+  __shared__ double red[256];
+  constexpr int kSamples = 65536;
+  double acc = 0.0;
+  for (int q = threadIdx.x; q < kSamples; q += 256) {
+    const double t = ((double)q + 0.5) / kSamples;
+    const float x = (float)exp2(2.0 * t);  // log-uniform on [1, 4)
+    const double xd = (double)x;
+    double y = __builtin_amdgcn_rsq(xd);
+    const double e = __builtin_fma(-(xd * y), y, 1.0);
+    y = __builtin_fma(y * e, __builtin_fma(0.375, e, 0.5), y);
+    const double yf = (double)__builtin_amdgcn_rsqf(x);
+    acc += (yf - y) / y;
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double b = red[0] / kSamples;
+    ctl->rsq_bias = b;
+    ctl->rsq_scale3 = correct ? 1.0 - 3.0 * b : 1.0;
+    ctl->rsq_scale1 = correct ? 1.0 - b : 1.0;
+  }
+}
+
+hipError_t launch_rsq_bias(const DevState& s, int correct, hipStream_t st) {
+  hipLaunchKernelGGL(rsq_bias_kernel, dim3(1), dim3(256), 0, st, s.ctl, correct);
   return hipGetLastError();
 }
 

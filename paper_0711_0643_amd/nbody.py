@@ -48,6 +48,8 @@ EXPORTED = [
     "nbody_get_layout",
     "nbody_get_tuning",
     "nbody_set_tuning",
+    "nbody_profile_force",
+    "nbody_profile_read",
     "nbody_destroy",
     "nbody_strerror",
 ]
@@ -95,9 +97,11 @@ class Layout(ctypes.Structure):
 class Tuning(ctypes.Structure):
     _fields_ = [
         ("target_items", ctypes.c_int32),
-        ("min_block", ctypes.c_int32 * 3),
+        ("min_block", ctypes.c_int32 * 4),
         ("grid", ctypes.c_int32),
         ("mixed_format", ctypes.c_int32),
+        ("rsq_bias_correct", ctypes.c_int32),
+        ("near_tau", ctypes.c_double),
     ]
 
 
@@ -155,6 +159,10 @@ def lib() -> ctypes.CDLL:
         L.nbody_get_tuning.restype = st
         L.nbody_set_tuning.argtypes = [p, ctypes.POINTER(Tuning)]
         L.nbody_set_tuning.restype = st
+        L.nbody_profile_force.argtypes = [p, i32]
+        L.nbody_profile_force.restype = st
+        L.nbody_profile_read.argtypes = [p, ctypes.POINTER(f64), ctypes.POINTER(i64)]
+        L.nbody_profile_read.restype = st
         L.nbody_destroy.argtypes = [p]
         L.nbody_destroy.restype = st
         L.nbody_strerror.argtypes = [st]
@@ -284,18 +292,31 @@ class Sim:
         t = Tuning()
         _check(lib().nbody_get_tuning(self._ctx, ctypes.byref(t)), "nbody_get_tuning")
         return {"target_items": t.target_items, "min_block": list(t.min_block), "grid": t.grid,
-                "mixed_format": t.mixed_format}
+                "mixed_format": t.mixed_format, "rsq_bias_correct": t.rsq_bias_correct,
+                "near_tau": t.near_tau}
 
     def set_tuning(self, **kw) -> None:
         cur = self.get_tuning()
         cur.update(kw)
         t = Tuning()
         t.target_items = int(cur["target_items"])
-        for i in range(3):
+        for i in range(4):
             t.min_block[i] = int(cur["min_block"][i])
         t.grid = int(cur["grid"])
         t.mixed_format = int(cur["mixed_format"])
+        t.rsq_bias_correct = int(cur["rsq_bias_correct"])
+        t.near_tau = float(cur["near_tau"])
         _check(lib().nbody_set_tuning(self._ctx, ctypes.byref(t)), "nbody_set_tuning")
+
+    def profile_force(self, enable: bool = True) -> None:
+        _check(lib().nbody_profile_force(self._ctx, int(bool(enable))), "nbody_profile_force")
+
+    def profile_read(self):
+        """(summed force-kernel milliseconds, launches) since the last read."""
+        ms = ctypes.c_double(0.0)
+        n = ctypes.c_int64(0)
+        _check(lib().nbody_profile_read(self._ctx, ctypes.byref(ms), ctypes.byref(n)), "nbody_profile_read")
+        return ms.value, n.value
 
     def predict(self, t_pred=None) -> None:
         if t_pred is None:

@@ -9,11 +9,11 @@ Tolerances:
                   j-ascending loop; 1e-12 leaves room for cancellation).
   mixed kernel -- acceleration and potential: per particle relative error
                   <= 1e-6 (the force-error bar); jerk: error measured against
-                  the sum of absolute jerk terms <= 1e-6 (FP32 pair terms
-                  carry ~5 u = 3e-7 each, and the jerk of a few particles
-                  cancels by a factor ~50), and per-particle relative error
-                  <= 1e-6 for every particle whose jerk cancels by less than
-                  a factor 10.
+                  the sum of absolute jerk terms K_i <= 1e-6.  FP32 pair terms
+                  carry a few units of u = 2^-24 each (about 3e-7), so the
+                  jerk error is bounded by ~5 u K_i; its relative error
+                  |dk|/|k| then scales with the cancellation K_i/|k_i|, which
+                  reaches ~50 in a Plummer sphere.
 """
 import numpy as np
 import pytest
@@ -56,9 +56,6 @@ def _check_mixed(got, ref, absum):
     assert ea.max() <= 1e-6, ea.max()
     ek_norm = normwise_err(k, rk, absum[1])
     assert ek_norm.max() <= 1e-6, ek_norm.max()
-    kappa_k = absum[1] / np.maximum(np.linalg.norm(rk, axis=0), 1e-300)
-    ek = rel_err(k, rk)
-    assert np.all(ek[kappa_k <= 10] <= 1e-6), ek[kappa_k <= 10].max()
     if p is not None:
         assert rel_err(p, rp).max() <= 1e-6, rel_err(p, rp).max()
 
@@ -194,13 +191,15 @@ def test_j_split_changes_only_rounding():
 
 
 def test_layout_variants_agree():
-    """Every i x j layout (1, 4, 16, 64 lanes per i) gives the oracle's sums."""
+    """Every i x j layout (2 i per lane; 1, 4, 16, 64 lanes per i) gives the
+    oracle's sums."""
     n = 2000
     m, x, v = icgen.plummer(n, 22)
     act = icgen.active_subset(n, 300)
     ref = oracle.force(m, x, v, 1 / n, act)
     sim = _sim(m, x, v, 1 / n, 0)
-    for mb in ([1, 1, 1], [100000, 1, 1], [100000, 100000, 1], [100000, 100000, 100000]):
+    big = 100000
+    for mb in ([1, 1, 1, 1], [big, 1, 1, 1], [big, big, 1, 1], [big, big, big, 1], [big, big, big, big]):
         banner(f"layout min_block={mb}")
         sim.set_tuning(min_block=mb)
         _check_fp64(_gpu_force(sim, act), ref)
@@ -237,27 +236,42 @@ def test_index_outside_cluster_is_reported():
 
 
 @pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
-def test_full_size_n65536_sampled(precision):
+def test_full_size_n65536_all_particles(precision):
     """Plummer N = 65536, eps = 1/N, every particle active (the launch the
-    benchmark times); the oracle checks a sample including the 200 most
-    central particles (strongest cancellation) and 100 random ones."""
+    benchmark times); every one of the 65536 results against the oracle."""
     n = 65536
     m, x, v = icgen.plummer(n, 3)
     eps = 1.0 / n
     banner(f"full size N=65536 precision={precision}")
     sim = _sim(m, x, v, eps, precision)
     act = np.arange(n, dtype=np.int32)
-    a, k, p = _gpu_force(sim, act)
-    r = np.sqrt((x * x).sum(0))
-    sample = np.unique(np.concatenate([np.argsort(r)[:200], np.random.default_rng(1).choice(n, 100, replace=False)]))
-    sample = sample.astype(np.int32)
-    ref = oracle.force(m, x, v, eps, sample)
-    got = (a[:, sample], k[:, sample], p[sample])
+    got = _gpu_force(sim, act)
+    ref = oracle.force(m, x, v, eps)
     if precision == 0:
         _check_fp64(got, ref)
     else:
-        _check_mixed(got, ref, oracle.force_abs(m, x, v, eps, sample))
+        _check_mixed(got, ref, oracle.force_abs(m, x, v, eps))
     # Newton's third law over the whole system (equal masses): sum a = 0
+    a = got[0]
     scale = np.abs(a).sum()
     assert np.abs(a.sum(axis=1)).max() <= (1e-13 if precision == 0 else 1e-6) * scale
+    sim.close()
+
+
+def test_mixed_near_pairs_in_fp64_fix_close_neighbours():
+    """With the FP64 treatment of near pairs off, the FP32 error of a single
+    dominant close-neighbour term exceeds 1e-6 relative for a few particles
+    of the N = 65536 Plummer sphere; with it on (default) none does."""
+    n = 65536
+    m, x, v = icgen.plummer(n, 3)
+    eps = 1.0 / n
+    banner("near pairs on/off")
+    sim = _sim(m, x, v, eps, 1)
+    act = np.arange(n, dtype=np.int32)
+    ref = oracle.force(m, x, v, eps)
+    ea_on = rel_err(_gpu_force(sim, act)[0], ref[0])
+    sim.set_tuning(near_tau=0.0)
+    ea_off = rel_err(_gpu_force(sim, act)[0], ref[0])
+    assert ea_on.max() <= 1e-6
+    assert ea_off.max() > ea_on.max()
     sim.close()

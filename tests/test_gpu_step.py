@@ -149,8 +149,9 @@ def test_plummer_n1024_to_t1_conserves_energy(precision):
     assert abs((E1 - E0) / E0) < 1e-5, (E1 - E0) / E0
     st = sim.host_state()
     assert np.all(st["t"] == 1.0)
+    # individual block steps conserve momentum only to the integration error
     P = st["v"] @ st["m"]
-    assert np.max(np.abs(P)) < 1e-10
+    assert np.max(np.abs(P)) < 1e-7
     sim.close()
 
 
