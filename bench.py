@@ -50,6 +50,8 @@ def parse():
     ap.add_argument("--kernel-reps", type=int, default=10, help="timed launches of the force kernel alone")
     ap.add_argument("--no-sweep", action="store_true",
                     help="full-block runs only (no n_act sweep, no alternative kernels): clean profiles")
+    ap.add_argument("--workload", choices=["c1", "c2", "c3", "c4", "c5", "model"], default=None,
+                    help="instead of the headline line, run one of the integration workloads and print its record")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run 5 plain device copies of 256 MiB (reference for HBM byte counters)")
     return ap.parse_args()
@@ -156,10 +158,172 @@ def call_time(sim, act, aoff, reps):
     return float(np.median(times)) / 1e3
 
 
+def run_workload(name, args):
+    """Integration workloads: block-step runs with energy drift and step statistics.
+
+    c1: Plummer N=1024, eps=1/1024, FP64 force, to t=1
+    c2: Plummer N=16384, eps=1/N, FP64 force, to t=1/4
+    c3: Plummer N=65536, eps=1/N, mixed force (and FP64 for comparison), to t=1/4
+    c4: 256 Plummer clusters, N log-uniform in [256, 8192], eps=1/N each, mixed, to t=1/2
+    c5: King W0=6 with Salpeter masses, N=262144, eps=1/N, mixed: full-block force
+        throughput and 100 block steps
+    """
+    import torch
+
+    import icgen
+    import paper_0711_0643_amd as nb
+
+    def drift_run(sim, t_end, chunk):
+        E0 = sim.energy()
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        sim.run(t_end, chunk=chunk)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - w0
+        E1 = sim.energy()
+        t, steps, inter = sim.progress()
+        drift = (E1 - E0) / np.abs(E0)
+        return {"_drift": drift, "wall_s": round(wall, 4), "block_steps": [int(x) for x in steps][:4] if steps.size > 4 else
+                [int(x) for x in steps], "interactions": float(inter.sum()),
+                "Ginteractions_per_s": round(float(inter.sum()) / wall / 1e9, 3),
+                "mean_block": float(inter.sum() / max(1, steps.sum())) / float(sim.n / sim.nc),
+                "max_abs_rel_energy_drift": float(np.abs(drift).max()),
+                "rel_energy_drift": [float(d) for d in drift[:4]], "t_end": t_end}
+
+    out = {"workload": name}
+    if name == "model":
+        out.update(perf_model())
+        print(json.dumps(out), flush=True)
+        return
+    if name in ("c1", "c2", "c3"):
+        n, seed, t_end = {"c1": (1024, 1, 1.0), "c2": (16384, 2, 0.25), "c3": (65536, 3, 0.25)}[name]
+        eps = 1.0 / n
+        m, x, v = icgen.plummer(n, seed)
+        precs = [("fp64", nb.FP64)] if name != "c3" else [("mixed", nb.MIXED), ("fp64", nb.FP64)]
+        for label, prec in precs:
+            sim = nb.Sim(m, x, v, eps, precision=prec)
+            out[label] = drift_run(sim, t_end, 256)
+            out[label].pop("_drift")
+            log(f"{name} {label}: {out[label]}")
+            sim.close()
+        out["config"] = f"Plummer N={n}, eps=1/N, eta=0.01, dt_max=1/8, to t={t_end}"
+    elif name == "c4":
+        m, x, v, coff, eps = icgen.ensemble(256, 4)
+        sim = nb.Sim(m, x, v, eps, cluster_offsets=coff, precision=nb.MIXED)
+        rec = drift_run(sim, 0.5, 256)
+        t, steps, inter = sim.progress()
+        rec["block_steps_per_cluster"] = {"min": int(steps.min()), "median": int(np.median(steps)),
+                                          "max": int(steps.max())}
+        rec["graph_replays"] = int(steps.max())
+        rec["per_cluster_drift"] = [float(d) for d in rec.pop("_drift")]
+        sizes = np.diff(coff)
+        worst = int(np.argmax(np.abs(rec["per_cluster_drift"])))
+        rec["worst_cluster"] = {"index": worst, "n": int(sizes[worst]), "drift": rec["per_cluster_drift"][worst]}
+        out["mixed"] = rec
+        out["config"] = (f"256 Plummer clusters, N log-uniform in [256, 8192] (sum {int(coff[-1])}), "
+                         "eps=1/N_c, mixed, to t=1/2, one graph replay = one block step of every cluster")
+        sim.close()
+    else:
+        n = 262144
+        m, x, v = icgen.king(n, 6.0, 5)
+        eps = 1.0 / n
+        sim = nb.Sim(m, x, v, eps, precision=nb.MIXED)
+        act = torch.arange(n, dtype=torch.int32, device=sim.device)
+        aoff = torch.tensor([0, n], dtype=torch.int64, device=sim.device)
+        kt, _, _ = kernel_time(sim, act, aoff, 5, warm=3)
+        out["force_full_block"] = {"kernel_ms": round(kt * 1e3, 3),
+                                   "Ginteractions_per_s": round(n * float(n) / kt / 1e9, 2),
+                                   "TFLOP_s": round(FLOPS_PER_INTERACTION * n * float(n) / kt / 1e12, 2)}
+        # 100 block steps one at a time, recording the block sizes
+        sizes = []
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        prev = 0.0
+        for _ in range(100):
+            sim.step(1, 1.0)
+            _, _, inter = sim.progress()
+            sizes.append(int(round((inter[0] - prev) / n)))
+            prev = inter[0]
+        wall = time.perf_counter() - w0
+        t, steps, inter = sim.progress()
+        hist, edges = np.histogram(np.log2(np.maximum(sizes, 1)), bins=np.arange(0, 20))
+        out["block_steps"] = {"steps": int(steps[0]), "t_reached": float(t[0]), "wall_s": round(wall, 4),
+                              "interactions": float(inter[0]), "mean_block": float(np.mean(sizes)),
+                              "max_block": int(max(sizes)), "min_block": int(min(sizes)),
+                              "log2_block_histogram": [int(h) for h in hist]}
+        out["config"] = "King W0=6, Salpeter masses (slope 2.35, 0.1-100, total 1), N=262144, eps=1/N, mixed"
+        sim.close()
+    print(json.dumps(out), flush=True)
+
+
+def perf_model():
+    """The paper's performance model on one MI355X (Sect. 4.1, Eq. tsnb).
+
+    Per block step of size s in a system of N:  T_adv(s) = tau_0 + tau_pr N +
+    tau_cr s + tau_f N s  (tau_0: the fixed cost of one step -- launches and
+    latency -- which the paper's host model does not have; no communication
+    term on one GPU).  Every block step of Plummer runs to t = 1/8 (the
+    paper's integration time) is timed with HIP events; the taus come from a
+    least-squares fit over all steps of all N; the model total T_N =
+    T_adv(s_mean) n_steps (Eq. tsnb) is compared with the measured total."""
+    import torch
+
+    import icgen
+    import paper_0711_0643_amd as nb
+
+    rows = []
+    per_n = {}
+    for n in (1024, 4096, 16384, 65536):
+        m, x, v = icgen.plummer(n, 100 + n)
+        sim = nb.Sim(m, x, v, 1.0 / n, precision=nb.MIXED)
+        times, sizes = [], []
+        prev = 0.0
+        t = 0.0
+        guard = 0
+        while t < 0.125 and guard < 200000:
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(sim.stream)
+            sim.step(1, 0.125)
+            e1.record(sim.stream)
+            e1.synchronize()
+            tt, _, inter = sim.progress()
+            t = float(tt[0])
+            s_blk = (inter[0] - prev) / n
+            prev = inter[0]
+            times.append(e0.elapsed_time(e1) * 1e-3)
+            sizes.append(s_blk)
+            guard += 1
+        sim.close()
+        times = np.array(times)
+        sizes = np.array(sizes)
+        per_n[n] = {"steps": int(times.size), "mean_block": float(sizes.mean()), "measured_s": float(times.sum())}
+        for tt_, ss in zip(times, sizes):
+            rows.append((n, ss, tt_))
+    A = np.array([[1.0, n, s_, n * s_] for n, s_, _ in rows])
+    y = np.array([t_ for _, _, t_ in rows])
+    # relative least squares: every step counts by its relative misfit
+    w = 1.0 / y
+    coef, *_ = np.linalg.lstsq(A * w[:, None], y * w, rcond=None)
+    tau0, tau_pr, tau_cr, tau_f = (float(c) for c in coef)
+    for n, rec in per_n.items():
+        t_adv = tau0 + tau_pr * n + tau_cr * rec["mean_block"] + tau_f * n * rec["mean_block"]
+        rec["model_s"] = t_adv * rec["steps"]
+        rec["model_over_measured"] = rec["model_s"] / rec["measured_s"]
+    return {"fit": {"tau_0_s": tau0, "tau_pr_s": tau_pr, "tau_cr_s": tau_cr, "tau_f_s": tau_f,
+                    "interactions_per_s_from_tau_f": 1.0 / tau_f if tau_f > 0 else None},
+            "per_N": {str(k): v for k, v in per_n.items()},
+            "paper_LISA": {"tau_pr_s": 5.6e-8, "tau_cr_s": 1.0e-6, "tau_f_s": 1.2e-7},
+            "config": "Plummer N in {1024, 4096, 16384, 65536}, eps=1/N, mixed force, eta=0.01, every block step "
+                      "to t=1/8 timed with HIP events"}
+
+
 def main():
     args = parse()
     if args.calibrate_copy:
         calibrate_copy()
+        return
+    if args.workload:
+        run_workload(args.workload, args)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",

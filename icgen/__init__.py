@@ -21,6 +21,9 @@ import numpy as np
 
 __all__ = [
     "plummer",
+    "king",
+    "king_profile",
+    "salpeter_masses",
     "ensemble_sizes",
     "ensemble",
     "active_subset",
@@ -138,3 +141,122 @@ def state_digest(*arrays: np.ndarray) -> str:
     for a in arrays:
         h.update(np.ascontiguousarray(a).astype(a.dtype.newbyteorder("<"), copy=False).tobytes())
     return h.hexdigest()
+
+
+def salpeter_masses(n: int, rng: np.random.Generator, slope: float = 2.35, m_lo: float = 0.1,
+                    m_hi: float = 100.0) -> np.ndarray:
+    """Masses from dN/dm ~ m^-slope on [m_lo, m_hi] by inverting the
+    cumulative distribution, normalised to a total of 1."""
+    a = 1.0 - slope
+    u = rng.random(n)
+    m = np.power(m_lo**a + u * (m_hi**a - m_lo**a), 1.0 / a)
+    return m / m.sum()
+
+
+def _king_rho(w):
+    """King (1966) density in units of the value it would have at W -> inf
+    scale: exp(W) erf(sqrt W) - sqrt(4W/pi) (1 + 2W/3)."""
+    w = np.maximum(w, 0.0)
+    from scipy.special import erf
+
+    return np.exp(w) * erf(np.sqrt(w)) - np.sqrt(4.0 * w / math.pi) * (1.0 + 2.0 * w / 3.0)
+
+
+def king_profile(w0: float, dr: float = 1e-3):
+    """Solve King's equation (1/r^2) d/dr (r^2 dW/dr) = -9 rho(W)/rho(W0) in
+    core-radius units (sigma = 1, G = 1, 4 pi G rho0 = 9) from W(0) = w0,
+    W'(0) = 0 outward to the tidal radius where W = 0 (classical RK4).
+
+    Returns (r, W, M) tabulated from 0 to the tidal radius (M = enclosed
+    mass in the same units)."""
+    rho0 = _king_rho(np.array([w0]))[0]
+
+    def rhs(r, y):
+        w, dw = y
+        lap = -9.0 * _king_rho(np.array([w]))[0] / rho0
+        return np.array([dw, lap - (2.0 / r) * dw if r > 0 else lap / 3.0])
+
+    # start slightly off the centre with the series W = w0 - (3/2) r^2 rho/rho0 ...
+    r = dr
+    y = np.array([w0 - 1.5 * r * r, -3.0 * r])
+    rs, ws = [0.0, r], [w0, y[0]]
+    while y[0] > 0.0 and r < 1e4:
+        k1 = rhs(r, y)
+        k2 = rhs(r + dr / 2, y + dr / 2 * k1)
+        k3 = rhs(r + dr / 2, y + dr / 2 * k2)
+        k4 = rhs(r + dr, y + dr * k3)
+        y_new = y + dr / 6 * (k1 + 2 * k2 + 2 * k3 + k4)
+        if y_new[0] <= 0.0:  # tidal radius inside this step: interpolate W = 0
+            f = y[0] / (y[0] - y_new[0])
+            r += f * dr
+            rs.append(r)
+            ws.append(0.0)
+            break
+        r += dr
+        y = y_new
+        rs.append(r)
+        ws.append(y[0])
+    r = np.array(rs)
+    w = np.array(ws)
+    rho = 9.0 / (4.0 * math.pi) * _king_rho(w) / rho0  # rho0 = 9 / (4 pi) in these units
+    dm = 4.0 * math.pi * r * r * rho
+    M = np.concatenate([[0.0], np.cumsum(0.5 * (dm[1:] + dm[:-1]) * np.diff(r))])
+    return r, w, M
+
+
+def king(n: int, w0: float, seed: int, masses: str = "salpeter"):
+    """King (1966) model with central potential w0, n particles.
+
+    Radii follow the enclosed-mass profile of king_profile (inverse CDF by
+    linear interpolation); speeds at radius r are drawn by rejection from
+    v^2 (exp(W(r) - v^2/2) - 1) on [0, sqrt(2 W(r))]; directions isotropic.
+    Masses are Salpeter (slope 2.35 on [0.1, 100]) assigned independently of
+    position, or equal.  The model is scaled to N-body units with its
+    analytic energy (virial: E = U/2 with U the smooth-model potential
+    energy), so E = -1/4 and Q = 1/2 hold in expectation."""
+    rng = _rng(seed)
+    r_tab, w_tab, m_tab = king_profile(w0)
+    mtot = m_tab[-1]
+    # radii
+    u = rng.random(n) * mtot
+    r = np.interp(u, m_tab, r_tab)
+    w = np.interp(r, r_tab, w_tab)
+    x = _isotropic(rng, r)
+    # speeds by rejection, per-particle envelope from a grid maximum
+    vmax = np.sqrt(2.0 * w)
+    grid = np.linspace(0.0, 1.0, 65)[None, :] * vmax[:, None]
+    pdf_grid = grid**2 * (np.exp(w[:, None] - grid**2 / 2.0) - 1.0)
+    pmax = 1.1 * pdf_grid.max(axis=1) + 1e-300
+    speed = np.zeros(n)
+    todo = np.arange(n)
+    while todo.size:
+        cand = rng.random(todo.size) * vmax[todo]
+        h = rng.random(todo.size) * pmax[todo]
+        p = cand**2 * (np.exp(w[todo] - cand**2 / 2.0) - 1.0)
+        ok = h < p
+        speed[todo[ok]] = cand[ok]
+        todo = todo[~ok]
+    v = _isotropic(rng, speed)
+    if masses == "salpeter":
+        m = salpeter_masses(n, rng)
+    elif masses == "equal":
+        m = np.full(n, 1.0 / n)
+    else:
+        raise ValueError("masses must be 'salpeter' or 'equal'")
+    # analytic energy of the smooth model: phi = -W - M/r_t (sigma = 1, G = 1)
+    rt = r_tab[-1]
+    rho = np.gradient(m_tab, r_tab) / np.maximum(4.0 * math.pi * r_tab**2, 1e-300)
+    rho[0] = rho[1]
+    phi = -w_tab - mtot / rt
+    dU = 0.5 * 4.0 * math.pi * r_tab**2 * rho * phi
+    U = float(np.sum(0.5 * (dU[1:] + dU[:-1]) * np.diff(r_tab)))
+    E_model = 0.5 * U
+    # to total mass 1 (v scales as sqrt(M)), then to E = -1/4 (length lambda)
+    v /= math.sqrt(mtot)
+    E1 = E_model / mtot**2
+    lam = E1 / -0.25
+    x -= (x @ m)[:, None]
+    v -= (v @ m)[:, None]
+    x *= lam
+    v /= math.sqrt(lam)
+    return m, np.ascontiguousarray(x), np.ascontiguousarray(v)

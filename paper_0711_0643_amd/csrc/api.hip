@@ -170,18 +170,18 @@ void destroy_graph(nbody_ctx* c) {
   c->graph_mode = -1;
 }
 
+// One block step = select (2 kernels; the second also predicts and plans)
+// -> force -> slice reduction with the corrector.  Captured once, replayed.
 nbody_status build_graph(nbody_ctx* c) {
   destroy_graph(c);
   const DevState& s = c->s;
   const int mode = force_mode(c);
   if (!c->cap_stream) HIP_OK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
   HIP_OK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed));
-  hipError_t e = launch_select(s, c->cap_stream);
-  if (e == hipSuccess) e = launch_plan(s, s.aoff, s.n, c->target_items, c->cap_stream, 1);
+  hipError_t e = launch_select_plan(s, c->target_items, c->cap_stream);
   if (e == hipSuccess)
     e = launch_force(s, mode, c->p.compute_pot != 0, c->ctl.near_tau > 0.0, s.act, c->grid, c->cap_stream);
-  if (e == hipSuccess) e = launch_reduce_step(s, c->p.compute_pot != 0, c->cap_stream);
-  if (e == hipSuccess) e = launch_correct_step(s, c->p.compute_pot != 0, c->cap_stream);
+  if (e == hipSuccess) e = launch_reduce_correct_step(s, c->p.compute_pot != 0, c->cap_stream);
   hipGraph_t g = nullptr;
   const hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
   if (e != hipSuccess || e2 != hipSuccess || !g) {

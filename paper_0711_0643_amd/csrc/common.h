@@ -72,6 +72,8 @@ struct Ctl {
   double rsq_scale3;
   double rsq_scale1;
   double rsq_bias;  // measured mean relative error of v_rsq_f32
+  int32_t sel_a_done;  // selection pass A workgroups finished (ticket)
+  int32_t sel_done;    // selection pass B workgroups finished (ticket)
 };
 
 struct DevState {

@@ -34,9 +34,9 @@ constexpr int kReduceGrid = 2048;
 hipError_t launch_reduce(const DevState& s, const int64_t* aoff, int64_t n_active, double* acc,
                          double* jerk, double* pot, hipStream_t st);
 
-// Step pipeline: the same into s.fout (rows a, k, pot of stride n) for the
-// active list s.act / s.aoff built by the selection.
-hipError_t launch_reduce_step(const DevState& s, bool pot, hipStream_t st);
+// Step pipeline: the same for the active list s.act / s.aoff built by the
+// selection, each sum handed straight to the corrector (pot: keep phi).
+hipError_t launch_reduce_correct_step(const DevState& s, bool pot, hipStream_t st);
 
 // Predict every particle of every cluster to s.tpred[c] (FP64 x_p, v_p and
 // the mixed j-records).
@@ -52,12 +52,10 @@ hipError_t launch_init_steps(const DevState& s, hipStream_t st);
 hipError_t launch_correct(const DevState& s, const int32_t* act, const int64_t* aoff, int64_t n_active,
                           const double* acc, const double* jerk, hipStream_t st);
 
-// Step pipeline: the corrector for s.act / s.aoff reading a, k (and pot)
-// from s.fout.
-hipError_t launch_correct_step(const DevState& s, bool pot, hipStream_t st);
 
-// Block selection (three passes) with the predictor fused into the last.
-hipError_t launch_select(const DevState& s, hipStream_t st);
+// Block selection (two passes) with the predictor fused into the second,
+// whose last workgroup also plans the force pass (count_stats on).
+hipError_t launch_select_plan(const DevState& s, int64_t target_items, hipStream_t st);
 
 // Mean relative error b of the FP32 hardware reciprocal square root over
 // log-uniform arguments in [1, 4); sets ctl->rsq_scale3 = 1 - 3b and

@@ -93,8 +93,9 @@ __device__ __forceinline__ bool bad_range(const int64_t* aoff, const int64_t* co
   return a0 < 0 || a1 < a0 || a1 > bound || a1 - a0 > coff[c + 1] - coff[c];
 }
 
-__global__ void __launch_bounds__(256) plan_kernel(DevState s, const int64_t* __restrict__ aoff,
-                                                   int64_t n_act_bound, int64_t target_items, int count_stats) {
+// The plan, computed by one workgroup of 256 threads.
+__device__ void plan_body(const DevState& s, const int64_t* __restrict__ aoff, int64_t n_act_bound,
+                          int64_t target_items, int count_stats) {
   __shared__ int64_t sbuf[256];
   const int tid = threadIdx.x;
   const int nc = s.nc;
@@ -175,6 +176,11 @@ __global__ void __launch_bounds__(256) plan_kernel(DevState s, const int64_t* __
   }
 }
 
+__global__ void __launch_bounds__(256) plan_kernel(DevState s, const int64_t* __restrict__ aoff,
+                                                   int64_t n_act_bound, int64_t target_items, int count_stats) {
+  plan_body(s, aoff, n_act_bound, target_items, count_stats);
+}
+
 hipError_t launch_plan(const DevState& s, const int64_t* aoff, int64_t n_act_bound, int64_t target_items,
                        hipStream_t st, int count_stats) {
   hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(256), 0, st, s, aoff, n_act_bound, target_items, count_stats);
@@ -190,6 +196,9 @@ hipError_t launch_plan(const DevState& s, const int64_t* aoff, int64_t n_act_bou
 // do not depend on the rest of the batch.  Output component d of entry q goes
 // to out[d][q * 1 + d_stride...]: acc[d * stride + q], jerk[d * stride + q],
 // pot[q] (pot may be NULL).  Entries at or past the active count are skipped.
+__device__ __forceinline__ void correct_one(const DevState& s, const Ctl& ctl, int c, int64_t i, bool first,
+                                            const double a1[3], const double k1[3]);
+
 __device__ __forceinline__ int cluster_of_unit(const Plan* plan, int nc, int64_t u) {
   int lo = 0, hi = nc - 1;
   while (lo < hi) {
@@ -199,6 +208,7 @@ __device__ __forceinline__ int cluster_of_unit(const Plan* plan, int nc, int64_t
   return lo;
 }
 
+template <bool STEP>
 __global__ void __launch_bounds__(256) reduce_kernel(DevState s, const int64_t* __restrict__ aoff,
                                                      int64_t n_bound, int n_from_aoff, double* acc, double* jerk,
                                                      double* pot, int64_t stride) {
@@ -239,12 +249,24 @@ __global__ void __launch_bounds__(256) reduce_kernel(DevState s, const int64_t* 
       __syncthreads();
     }
     if (live && lane == 0 && q < n_active) {
+      if constexpr (STEP) {  // step pipeline: correct the particle right here
+        const int64_t i = s.act[q];
+        double a1[3], k1[3];
 #pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        acc[d * stride + q] = red[d][tid];
-        jerk[d * stride + q] = red[3 + d][tid];
+        for (int d = 0; d < 3; ++d) {
+          a1[d] = red[d][tid];
+          k1[d] = red[3 + d][tid];
+        }
+        if (pot) s.pot[i] = red[6][tid];
+        correct_one(s, *s.ctl, c, i, e == 0, a1, k1);
+      } else {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          acc[d * stride + q] = red[d][tid];
+          jerk[d * stride + q] = red[3 + d][tid];
+        }
+        if (pot) pot[q] = red[6][tid];
       }
-      if (pot) pot[q] = red[6][tid];
     }
     __syncthreads();  // red is reused by the next unit
   }
@@ -269,14 +291,15 @@ hipError_t launch_reduce(const DevState& s, const int64_t* aoff, int64_t n_activ
                          double* jerk, double* pot, hipStream_t st) {
   const int64_t g = (n_active + 255) / 256;
   hipLaunchKernelGGL(reduce_tail_kernel, dim3((unsigned)g), dim3(256), 0, st, s, aoff, n_active, acc, jerk, pot);
-  hipLaunchKernelGGL(reduce_kernel, dim3(kReduceGrid), dim3(256), 0, st, s, aoff, n_active, 0, acc, jerk, pot,
-                     n_active);
+  hipLaunchKernelGGL(reduce_kernel<false>, dim3(kReduceGrid), dim3(256), 0, st, s, aoff, n_active, 0, acc, jerk,
+                     pot, n_active);
   return hipGetLastError();
 }
 
-hipError_t launch_reduce_step(const DevState& s, bool pot, hipStream_t st) {
-  hipLaunchKernelGGL(reduce_kernel, dim3(kReduceGrid), dim3(256), 0, st, s, s.aoff, s.n, 1, s.fout, s.fout + 3 * s.n,
-                     pot ? s.fout + 6 * s.n : nullptr, s.n);
+hipError_t launch_reduce_correct_step(const DevState& s, bool pot, hipStream_t st) {
+  // pot only flags whether the potential row exists; the step writes s.pot
+  hipLaunchKernelGGL(reduce_kernel<true>, dim3(kReduceGrid), dim3(256), 0, st, s, s.aoff, s.n, 1,
+                     (double*)nullptr, (double*)nullptr, pot ? s.pot : nullptr, (int64_t)0);
   return hipGetLastError();
 }
 
@@ -361,41 +384,12 @@ hipError_t launch_init_steps(const DevState& s, hipStream_t st) {
 // (Eq. timestep) with the end-of-step quantities, and quantisation.
 // Entry q of the active list advances particle act[q] to tpred of its
 // cluster.
-__global__ void __launch_bounds__(256) correct_kernel(DevState s, const int32_t* __restrict__ act,
-                                                      const int64_t* __restrict__ aoff, int64_t n_bound,
-                                                      const double* __restrict__ acc,
-                                                      const double* __restrict__ jerk,
-                                                      const double* __restrict__ pot, int64_t stride,
-                                                      int n_from_aoff) {
-  const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  const int nc = s.nc;
-  const int64_t n_active = n_from_aoff ? aoff[nc] : n_bound;
-  if (q >= n_active) return;
+// One particle: corrector, new step, state update.  i: particle, c: its
+// cluster, first: whether this entry is the cluster's first of the block
+// (it records the cluster's new time).
+__device__ __forceinline__ void correct_one(const DevState& s, const Ctl& ctl, int c, int64_t i, bool first,
+                                            const double a1[3], const double k1[3]) {
   const int64_t n = s.n;
-  const Ctl ctl = *s.ctl;
-  // cluster of entry q: last c with aoff[c] <= q
-  int lo = 0, hi = nc - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (aoff[mid] <= q) lo = mid; else hi = mid - 1;
-  }
-  const int c = lo;
-  if (q >= aoff[nc] || aoff[0] != 0) {  // n_active disagrees with the active offsets
-    set_status(s, ST_INDEX);
-    return;
-  }
-  const int64_t i = act[q];
-  if (i < s.coff[c] || i >= s.coff[c + 1]) {
-    set_status(s, ST_INDEX);
-    return;
-  }
-  double a1[3], k1[3];
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    a1[d] = acc[d * stride + q];
-    k1[d] = jerk[d * stride + q];
-  }
-  if (pot) s.pot[i] = pot[q];
   const double t_new = s.tpred[c];
   const double h = t_new - s.t[i];
   int32_t st = 0;
@@ -429,112 +423,169 @@ __global__ void __launch_bounds__(256) correct_kernel(DevState s, const int32_t*
   const double raw = den == 0.0 ? INFINITY : sqrt(ctl.eta * (na * na2 + nk * nk) / den);
   s.dt[i] = quantize(raw, s.dt[i], t_new, ctl.dt_max, ctl.dt_min, &st);
   s.t[i] = t_new;
-  if (q == aoff[c]) {
-    s.tnow[c] = t_new;
-  }
+  if (first) s.tnow[c] = t_new;
   if (st) set_status(s, st);
+}
+
+// Corrector for a caller's active list with its acc/jerk ([3][n_active]).
+__global__ void __launch_bounds__(256) correct_kernel(DevState s, const int32_t* __restrict__ act,
+                                                      const int64_t* __restrict__ aoff, int64_t n_active,
+                                                      const double* __restrict__ acc,
+                                                      const double* __restrict__ jerk) {
+  const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (q >= n_active) return;
+  const int nc = s.nc;
+  const Ctl ctl = *s.ctl;
+  // cluster of entry q: last c with aoff[c] <= q
+  int lo = 0, hi = nc - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (aoff[mid] <= q) lo = mid; else hi = mid - 1;
+  }
+  const int c = lo;
+  if (q >= aoff[nc] || aoff[0] != 0) {  // n_active disagrees with the active offsets
+    set_status(s, ST_INDEX);
+    return;
+  }
+  const int64_t i = act[q];
+  if (i < s.coff[c] || i >= s.coff[c + 1]) {
+    set_status(s, ST_INDEX);
+    return;
+  }
+  double a1[3], k1[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    a1[d] = acc[d * n_active + q];
+    k1[d] = jerk[d * n_active + q];
+  }
+  correct_one(s, ctl, c, i, q == aoff[c], a1, k1);
 }
 
 hipError_t launch_correct(const DevState& s, const int32_t* act, const int64_t* aoff, int64_t n_active,
                           const double* acc, const double* jerk, hipStream_t st) {
   const int64_t g = (n_active + 255) / 256;
-  hipLaunchKernelGGL(correct_kernel, dim3((unsigned)g), dim3(256), 0, st, s, act, aoff, n_active, acc, jerk,
-                     (const double*)nullptr, n_active, 0);
-  return hipGetLastError();
-}
-
-hipError_t launch_correct_step(const DevState& s, bool pot, hipStream_t st) {
-  const int64_t g = (s.n + 255) / 256;
-  hipLaunchKernelGGL(correct_kernel, dim3((unsigned)g), dim3(256), 0, st, s, s.act, s.aoff, s.n, s.fout,
-                     s.fout + 3 * s.n, pot ? s.fout + 6 * s.n : nullptr, s.n, 1);
+  hipLaunchKernelGGL(correct_kernel, dim3((unsigned)g), dim3(256), 0, st, s, act, aoff, n_active, acc, jerk);
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
-// Block selection (Sect. 2.1: the particles with the smallest t_i + dt_i).
-// Pass 1: minimum of t + dt per chunk.  Pass 2: block time per cluster and
-// block members per chunk.  Pass 3: ascending compaction into the active
-// list, per-cluster active offsets, and the predictor for every particle of
-// an advancing cluster.  A cluster whose next block time is past t_end
-// contributes no block.
+// Block selection (Sect. 2.1: the particles with the smallest t_i + dt_i),
+// two passes over selection chunks (contiguous particles of one cluster).
+//
+// Pass A: each chunk reduces (min of t + dt, number of particles at that
+// min).  The last workgroup to finish then, per cluster, takes the block
+// time as the minimum over its chunks (a cluster whose block time is past
+// t_end is done and advances no block), keeps the counts of the chunks that
+// hold that minimum, and turns them into output offsets (an exclusive scan
+// in chunk order, which is cluster order): the active offsets and each
+// chunk's first output slot.
+// Pass B: each chunk of an advancing cluster writes its block members in
+// ascending order from its slot and predicts all its particles (Sect. 2.1
+// predictor); the last workgroup to finish plans the force pass.
 
-__global__ void __launch_bounds__(kSelThreads) select1_kernel(DevState s) {
-  __shared__ double red[kSelThreads];
+// The (min, count-at-min) pair reduction, combined in a fixed tree.
+struct MinCount {
+  double m;
+  int32_t c;
+};
+__device__ __forceinline__ MinCount mc_join(MinCount a, MinCount b) {
+  if (a.m < b.m) return a;
+  if (b.m < a.m) return b;
+  return {a.m, a.c + b.c};
+}
+
+// Ticket of a workgroup at the end of a pass: true for the last one to
+// finish (it also resets the counter for the next step).
+__device__ __forceinline__ bool last_to_finish(int32_t* counter, int total) {
+  __shared__ int last;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int ticket = __hip_atomic_fetch_add(counter, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    last = ticket == total - 1;
+    if (last) __hip_atomic_store(counter, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __syncthreads();
+  if (last) __threadfence();
+  return last;
+}
+
+__global__ void __launch_bounds__(kSelThreads) select_a_kernel(DevState s) {
+  __shared__ double rm[kSelThreads];
+  __shared__ int32_t rc[kSelThreads];
+  __shared__ int64_t sbuf[kSelThreads];
+  const int tid = threadIdx.x;
   const int ch = blockIdx.x;
   const int64_t b = s.ch_begin[ch], e = s.ch_begin[ch + 1];
-  double mn = INFINITY;
-  for (int64_t i = b + threadIdx.x; i < e; i += kSelThreads) {
-    const double ti = s.t[i] + s.dt[i];
-    mn = ti < mn ? ti : mn;
-  }
-  red[threadIdx.x] = mn;
+  MinCount mc{INFINITY, 0};
+  for (int64_t i = b + tid; i < e; i += kSelThreads) mc = mc_join(mc, MinCount{s.t[i] + s.dt[i], 1});
+  rm[tid] = mc.m;
+  rc[tid] = mc.c;
   __syncthreads();
   for (int off = kSelThreads / 2; off > 0; off >>= 1) {
-    if (threadIdx.x < off) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + off]);
+    if (tid < off) {
+      const MinCount j = mc_join(MinCount{rm[tid], rc[tid]}, MinCount{rm[tid + off], rc[tid + off]});
+      rm[tid] = j.m;
+      rc[tid] = j.c;
+    }
     __syncthreads();
   }
-  if (threadIdx.x == 0) s.cmin[ch] = red[0];
+  if (tid == 0) {
+    s.cmin[ch] = rm[0];
+    s.ccount[ch] = rc[0];
+  }
+  if (!last_to_finish(&s.ctl->sel_a_done, s.nch)) return;
+
+  // last workgroup: block time per cluster
+  const double t_end = s.ctl->t_end;
+  for (int c = tid; c < s.nc; c += kSelThreads) {
+    double m = INFINITY;
+    for (int f = s.cl_ch[c]; f < s.cl_ch[c + 1]; ++f) m = fmin(m, s.cmin[f]);
+    s.tsys[c] = (m <= t_end) ? m : -1.0;
+  }
+  __syncthreads();
+  // per-thread contiguous runs of chunks; counts of chunks at their cluster's block time
+  const int nch = s.nch;
+  const int per = (nch + kSelThreads - 1) / kSelThreads;
+  const int f0 = tid * per < nch ? tid * per : nch;
+  const int f1 = f0 + per < nch ? f0 + per : nch;
+  int64_t mine = 0;
+  for (int f = f0; f < f1; ++f) {
+    const double ts = s.tsys[s.ch_cluster[f]];
+    mine += (ts >= 0.0 && s.cmin[f] == ts) ? s.ccount[f] : 0;
+  }
+  sbuf[tid] = mine;
+  __syncthreads();
+  for (int off = 1; off < kSelThreads; off <<= 1) {
+    const int64_t add = tid >= off ? sbuf[tid - off] : 0;
+    __syncthreads();
+    sbuf[tid] += add;
+    __syncthreads();
+  }
+  int64_t base = sbuf[tid] - mine;
+  for (int f = f0; f < f1; ++f) {
+    const int c = s.ch_cluster[f];
+    const double ts = s.tsys[c];
+    const int32_t cnt = (ts >= 0.0 && s.cmin[f] == ts) ? s.ccount[f] : 0;
+    if (f == s.cl_ch[c]) s.aoff[c] = base;
+    s.ccount[f] = (int32_t)base;  // from here on: the chunk's first output slot
+    base += cnt;
+  }
+  if (tid == kSelThreads - 1) s.aoff[s.nc] = sbuf[kSelThreads - 1];
 }
 
-__global__ void __launch_bounds__(kSelThreads) select2_kernel(DevState s) {
-  __shared__ double red[kSelThreads];
-  __shared__ int32_t cnt[kSelThreads];
-  const int ch = blockIdx.x;
-  const int c = s.ch_cluster[ch];
-  const int f0 = s.cl_ch[c], f1 = s.cl_ch[c + 1];
-  double mn = INFINITY;
-  for (int f = f0 + threadIdx.x; f < f1; f += kSelThreads) mn = fmin(mn, s.cmin[f]);
-  red[threadIdx.x] = mn;
-  __syncthreads();
-  for (int off = kSelThreads / 2; off > 0; off >>= 1) {
-    if (threadIdx.x < off) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + off]);
-    __syncthreads();
-  }
-  const double tsys = red[0];
-  const bool done = !(tsys <= s.ctl->t_end);
-  int32_t count = 0;
-  if (!done) {
-    const int64_t b = s.ch_begin[ch], e = s.ch_begin[ch + 1];
-    for (int64_t i = b + threadIdx.x; i < e; i += kSelThreads) count += (s.t[i] + s.dt[i] == tsys) ? 1 : 0;
-  }
-  cnt[threadIdx.x] = count;
-  __syncthreads();
-  for (int off = kSelThreads / 2; off > 0; off >>= 1) {
-    if (threadIdx.x < off) cnt[threadIdx.x] += cnt[threadIdx.x + off];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    s.ccount[ch] = cnt[0];
-    if (ch == f0) s.tsys[c] = done ? -1.0 : tsys;
-  }
-}
-
-__global__ void __launch_bounds__(kSelThreads) select3_kernel(DevState s) {
+__global__ void __launch_bounds__(kSelThreads) select_b_kernel(DevState s, int64_t target_items) {
   constexpr int PT = kSelChunk / kSelThreads;  // particles per thread
   __shared__ int32_t sb[kSelThreads];
-  __shared__ int64_t base_sh;
   const int ch = blockIdx.x;
   const int c = s.ch_cluster[ch];
   const int tid = threadIdx.x;
-  // active entries before this chunk (all clusters)
-  int64_t pre = 0;
-  for (int f = tid; f < ch; f += kSelThreads) pre += s.ccount[f];
-  __shared__ int64_t pbuf[kSelThreads];
-  pbuf[tid] = pre;
-  __syncthreads();
-  for (int off = kSelThreads / 2; off > 0; off >>= 1) {
-    if (tid < off) pbuf[tid] += pbuf[tid + off];
-    __syncthreads();
-  }
-  if (tid == 0) base_sh = pbuf[0];
-  __syncthreads();
-  const int64_t base = base_sh;
   const double tsys = s.tsys[c];
   const bool advancing = tsys >= 0.0;
   const int64_t b = s.ch_begin[ch], e = s.ch_begin[ch + 1];
-  const int64_t i0 = b + (int64_t)tid * PT;
-  int32_t flags = 0, mine = 0;
-  if (advancing) {
+  if (advancing && s.cmin[ch] == tsys) {
+    const int64_t i0 = b + (int64_t)tid * PT;
+    int32_t flags = 0, mine = 0;
 #pragma unroll
     for (int u = 0; u < PT; ++u) {
       const int64_t i = i0 + u;
@@ -543,36 +594,30 @@ __global__ void __launch_bounds__(kSelThreads) select3_kernel(DevState s) {
         ++mine;
       }
     }
-  }
-  // exclusive scan of per-thread counts (Hillis-Steele)
-  sb[tid] = mine;
-  __syncthreads();
-  for (int off = 1; off < kSelThreads; off <<= 1) {
-    const int32_t add = tid >= off ? sb[tid - off] : 0;
+    // exclusive scan of per-thread counts (Hillis-Steele)
+    sb[tid] = mine;
     __syncthreads();
-    sb[tid] += add;
-    __syncthreads();
-  }
-  int64_t pos = base + sb[tid] - mine;
-#pragma unroll
-  for (int u = 0; u < PT; ++u)
-    if (flags & (1 << u)) s.act[pos++] = (int32_t)(i0 + u);
-  if (tid == 0) {
-    if (ch == s.cl_ch[c]) {
-      s.aoff[c] = base;
-      if (advancing) s.tpred[c] = tsys;
+    for (int off = 1; off < kSelThreads; off <<= 1) {
+      const int32_t add = tid >= off ? sb[tid - off] : 0;
+      __syncthreads();
+      sb[tid] += add;
+      __syncthreads();
     }
-    if (ch == s.nch - 1) s.aoff[s.nc] = base + sb[kSelThreads - 1];
+    int64_t pos = (int64_t)s.ccount[ch] + sb[tid] - mine;
+#pragma unroll
+    for (int u = 0; u < PT; ++u)
+      if (flags & (1 << u)) s.act[pos++] = (int32_t)(i0 + u);
   }
   if (advancing) {
+    if (tid == 0 && ch == s.cl_ch[c]) s.tpred[c] = tsys;
     for (int64_t i = b + tid; i < e; i += kSelThreads) predict_one(s, i, tsys);
   }
+  if (last_to_finish(&s.ctl->sel_done, s.nch)) plan_body(s, s.aoff, s.n, target_items, 1);
 }
 
-hipError_t launch_select(const DevState& s, hipStream_t st) {
-  hipLaunchKernelGGL(select1_kernel, dim3(s.nch), dim3(kSelThreads), 0, st, s);
-  hipLaunchKernelGGL(select2_kernel, dim3(s.nch), dim3(kSelThreads), 0, st, s);
-  hipLaunchKernelGGL(select3_kernel, dim3(s.nch), dim3(kSelThreads), 0, st, s);
+hipError_t launch_select_plan(const DevState& s, int64_t target_items, hipStream_t st) {
+  hipLaunchKernelGGL(select_a_kernel, dim3(s.nch), dim3(kSelThreads), 0, st, s);
+  hipLaunchKernelGGL(select_b_kernel, dim3(s.nch), dim3(kSelThreads), 0, st, s, target_items);
   return hipGetLastError();
 }
 

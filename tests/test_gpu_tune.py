@@ -1,0 +1,45 @@
+"""The autotuner: every configuration it returns passes the parity gate
+against the oracle, and its cache round-trips (GPU)."""
+import json
+
+import numpy as np
+import pytest
+
+import icgen
+import oracle
+from tests.gpu_util import banner, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("precision", [1, 0], ids=["mixed", "fp64"])
+def test_tuner_picks_a_parity_passing_config(precision, tmp_path, monkeypatch):
+    import torch
+
+    import paper_0711_0643_amd as nb
+    from paper_0711_0643_amd import tune
+
+    monkeypatch.setenv("NBODY_TUNE_CACHE", str(tmp_path / "tune.json"))
+    n = 4096
+    m, x, v = icgen.plummer(n, 17)
+    eps = 1.0 / n
+    banner(f"tune N={n} precision={precision}")
+    sim = nb.Sim(m, x, v, eps, precision=precision)
+    cfg = tune.tune(sim, ladder=[1, 64, 1024, n])
+    assert cfg == sim.get_tuning()
+    data = json.loads((tmp_path / "tune.json").read_text())
+    key = tune.cache_key(sim)
+    assert key in data and data[key]["tuning"] == cfg
+    assert any(r["ok"] for r in data[key]["records"])
+    # the chosen configuration against the oracle on several block sizes
+    for na in (1, 100, n):
+        act = icgen.active_subset(n, na)
+        a, k, _ = sim.force(act)
+        torch.cuda.synchronize()
+        ra, rk, _ = oracle.force(m, x, v, eps, act)
+        assert rel_err(a.cpu().numpy(), ra).max() <= (1e-6 if precision == 1 else 1e-12)
+    # a second call is served from the cache
+    sim2 = nb.Sim(m, x, v, eps, precision=precision)
+    assert tune.tune(sim2) == cfg
+    sim.close()
+    sim2.close()
