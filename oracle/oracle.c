@@ -397,7 +397,10 @@ void oracle_diagnostics(int64_t n, const double *m, const double *x, const doubl
         l[1] += m[i] * (xi[2] * vi[0] - xi[0] * vi[2]);
         l[2] += m[i] * (xi[0] * vi[1] - xi[1] * vi[0]);
     }
-#pragma omp parallel for reduction(+ : pe) schedule(dynamic, 16)
+    /* per-particle potentials in parallel, then summed in index order so
+     * the result does not depend on the number of threads */
+    double *phi = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+#pragma omp parallel for schedule(dynamic, 16)
     for (int64_t i = 0; i < n; ++i) {
         double s = 0.0;
         for (int64_t j = 0; j < n; ++j) {
@@ -405,8 +408,10 @@ void oracle_diagnostics(int64_t n, const double *m, const double *x, const doubl
             const double dx = x[j] - x[i], dy = x[n + j] - x[n + i], dz = x[2 * n + j] - x[2 * n + i];
             s -= m[j] / sqrt(dx * dx + dy * dy + dz * dz + eps2);
         }
-        pe += 0.5 * m[i] * s;
+        if (phi) phi[i] = s;
     }
+    for (int64_t i = 0; i < n && phi; ++i) pe += 0.5 * m[i] * phi[i];
+    free(phi);
     out[0] = ke;
     out[1] = pe;
     out[2] = p[0]; out[3] = p[1]; out[4] = p[2];
