@@ -190,7 +190,8 @@ NBODY_API nbody_status nbody_get_layout(const nbody_ctx *ctx, nbody_layout *out)
  * its own size, its block size and these values (never on other clusters
  * in the batch); changing them changes force sums at rounding level only.
  *   target_items: work items (i-chunk x j-slice) a cluster's force pass is
- *                 split into when it has enough tiles (default: 8 per CU).
+ *                 split into when it has enough tiles (default: 8 per CU;
+ *                 1 .. 16384).
  *   min_block: smallest block size that uses, in order, the layouts with
  *              two i per lane, one i per lane, 4 lanes per i and 16 lanes
  *              per i (default 384, 192, 48, 12); smaller blocks use 64

@@ -170,8 +170,8 @@ void destroy_graph(nbody_ctx* c) {
   c->graph_mode = -1;
 }
 
-// One block step = select (2 kernels; the second also predicts and plans)
-// -> force -> slice reduction with the corrector.  Captured once, replayed.
+// One block step = select (3 kernels; the last also predicts) -> plan ->
+// force -> slice reduction with the corrector.  Captured once, replayed.
 nbody_status build_graph(nbody_ctx* c) {
   destroy_graph(c);
   const DevState& s = c->s;
@@ -561,7 +561,8 @@ nbody_status nbody_get_tuning(const nbody_ctx* c, nbody_tuning* t) {
 
 nbody_status nbody_set_tuning(nbody_ctx* c, const nbody_tuning* t) {
   if (!c || !t) return NBODY_E_INVAL;
-  if (t->target_items < 1 || t->grid < 1 || t->grid > (1 << 20)) return NBODY_E_INVAL;
+  if (t->target_items < 1 || t->target_items > kMaxTargetItems || t->grid < 1 || t->grid > (1 << 20))
+    return NBODY_E_INVAL;
   if (t->mixed_format != 0 && t->mixed_format != 1) return NBODY_E_INVAL;
   if (t->rsq_bias_correct != 0 && t->rsq_bias_correct != 1) return NBODY_E_INVAL;
   if (!(t->near_tau >= 0.0) || !isfinite(t->near_tau)) return NBODY_E_INVAL;

@@ -24,6 +24,8 @@ enum : int32_t {
 constexpr int kForceThreads = 256;
 // j-records staged in LDS per tile.
 constexpr int kTile = 256;
+// Largest slicing target a plan may be asked for.
+constexpr int64_t kMaxTargetItems = 16384;
 // Partial-row budget: a cluster of N particles may use up to
 // kRowsPerParticle * N + kRowsPerCluster rows of slice partials.
 constexpr int64_t kRowsPerParticle = 32;
@@ -72,8 +74,7 @@ struct Ctl {
   double rsq_scale3;
   double rsq_scale1;
   double rsq_bias;  // measured mean relative error of v_rsq_f32
-  int32_t sel_a_done;  // selection pass A workgroups finished (ticket)
-  int32_t sel_done;    // selection pass B workgroups finished (ticket)
+  int32_t pad3[2];
 };
 
 struct DevState {

@@ -355,8 +355,8 @@ __device__ __forceinline__ void sweep_tile(const typename ModeT<MODE>::Rec* tile
   }
 }
 
-// Locate the cluster that owns work item `item` (plans are ordered by
-// cluster; item_off is ascending).
+// Cluster of work item `item`: the last cluster whose item_off <= item
+// (plans are in cluster order, item_off ascending).
 __device__ __forceinline__ int find_cluster(const Plan* plan, int nc, int64_t item) {
   int lo = 0, hi = nc - 1;
   while (lo < hi) {

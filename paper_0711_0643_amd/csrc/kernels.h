@@ -53,8 +53,8 @@ hipError_t launch_correct(const DevState& s, const int32_t* act, const int64_t* 
                           const double* acc, const double* jerk, hipStream_t st);
 
 
-// Block selection (two passes) with the predictor fused into the second,
-// whose last workgroup also plans the force pass (count_stats on).
+// Block selection (three passes, the predictor fused into the last) and the
+// plan of the force pass (count_stats on).
 hipError_t launch_select_plan(const DevState& s, int64_t target_items, hipStream_t st);
 
 // Mean relative error b of the FP32 hardware reciprocal square root over

@@ -165,7 +165,7 @@ __device__ void plan_body(const DevState& s, const int64_t* __restrict__ aoff, i
     bu += (P.n_act + (256 / P.red_tp) - 1) / (256 / P.red_tp);
   }
   if (tid == 0) {
-    if (tot_rows > s.rows_cap) {  // cannot happen with the bounds above; refuse the pass
+    if (tot_rows > s.rows_cap) {  // cannot happen with the bounds of the plan; refuse the pass
       set_status(s, ST_INDEX);
       tot_items = 0;
       tot_red = 0;
@@ -193,12 +193,13 @@ hipError_t launch_plan(const DevState& s, const int64_t* aoff, int64_t n_act_bou
 // power of two, at most 256).  Lane l adds slices l, l + TP, ... in order;
 // the TP lane sums are then combined by a fixed binary tree in LDS.  TP and
 // the order depend only on the cluster's own plan, so the bits of a cluster
-// do not depend on the rest of the batch.  Output component d of entry q goes
-// to out[d][q * 1 + d_stride...]: acc[d * stride + q], jerk[d * stride + q],
-// pot[q] (pot may be NULL).  Entries at or past the active count are skipped.
+// do not depend on the rest of the batch.  Outputs: acc[d * stride + q],
+// jerk[d * stride + q], pot[q] (pot may be NULL); entries at or past the
+// active count are skipped.  STEP: the sums go straight to the corrector.
 __device__ __forceinline__ void correct_one(const DevState& s, const Ctl& ctl, int c, int64_t i, bool first,
                                             const double a1[3], const double k1[3]);
 
+// Cluster of reduce unit u: the last cluster whose red_off <= u.
 __device__ __forceinline__ int cluster_of_unit(const Plan* plan, int nc, int64_t u) {
   int lo = 0, hi = nc - 1;
   while (lo < hi) {
@@ -469,123 +470,90 @@ hipError_t launch_correct(const DevState& s, const int32_t* act, const int64_t* 
 }
 
 // ---------------------------------------------------------------------------
-// Block selection (Sect. 2.1: the particles with the smallest t_i + dt_i),
-// two passes over selection chunks (contiguous particles of one cluster).
-//
-// Pass A: each chunk reduces (min of t + dt, number of particles at that
-// min).  The last workgroup to finish then, per cluster, takes the block
-// time as the minimum over its chunks (a cluster whose block time is past
-// t_end is done and advances no block), keeps the counts of the chunks that
-// hold that minimum, and turns them into output offsets (an exclusive scan
-// in chunk order, which is cluster order): the active offsets and each
-// chunk's first output slot.
-// Pass B: each chunk of an advancing cluster writes its block members in
-// ascending order from its slot and predicts all its particles (Sect. 2.1
-// predictor); the last workgroup to finish plans the force pass.
+// Block selection (Sect. 2.1: the particles with the smallest t_i + dt_i).
+// Pass 1: minimum of t + dt per chunk.  Pass 2: block time per cluster and
+// block members per chunk.  Pass 3: ascending compaction into the active
+// list, per-cluster active offsets, and the predictor for every particle of
+// an advancing cluster.  A cluster whose next block time is past t_end
+// contributes no block.
 
-// The (min, count-at-min) pair reduction, combined in a fixed tree.
-struct MinCount {
-  double m;
-  int32_t c;
-};
-__device__ __forceinline__ MinCount mc_join(MinCount a, MinCount b) {
-  if (a.m < b.m) return a;
-  if (b.m < a.m) return b;
-  return {a.m, a.c + b.c};
-}
-
-// Ticket of a workgroup at the end of a pass: true for the last one to
-// finish (it also resets the counter for the next step).
-__device__ __forceinline__ bool last_to_finish(int32_t* counter, int total) {
-  __shared__ int last;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const int ticket = __hip_atomic_fetch_add(counter, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    last = ticket == total - 1;
-    if (last) __hip_atomic_store(counter, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
-  __syncthreads();
-  if (last) __threadfence();
-  return last;
-}
-
-__global__ void __launch_bounds__(kSelThreads) select_a_kernel(DevState s) {
-  __shared__ double rm[kSelThreads];
-  __shared__ int32_t rc[kSelThreads];
-  __shared__ int64_t sbuf[kSelThreads];
-  const int tid = threadIdx.x;
+__global__ void __launch_bounds__(kSelThreads) select1_kernel(DevState s) {
+  __shared__ double red[kSelThreads];
   const int ch = blockIdx.x;
   const int64_t b = s.ch_begin[ch], e = s.ch_begin[ch + 1];
-  MinCount mc{INFINITY, 0};
-  for (int64_t i = b + tid; i < e; i += kSelThreads) mc = mc_join(mc, MinCount{s.t[i] + s.dt[i], 1});
-  rm[tid] = mc.m;
-  rc[tid] = mc.c;
+  double mn = INFINITY;
+  for (int64_t i = b + threadIdx.x; i < e; i += kSelThreads) {
+    const double ti = s.t[i] + s.dt[i];
+    mn = ti < mn ? ti : mn;
+  }
+  red[threadIdx.x] = mn;
   __syncthreads();
   for (int off = kSelThreads / 2; off > 0; off >>= 1) {
-    if (tid < off) {
-      const MinCount j = mc_join(MinCount{rm[tid], rc[tid]}, MinCount{rm[tid + off], rc[tid + off]});
-      rm[tid] = j.m;
-      rc[tid] = j.c;
-    }
+    if (threadIdx.x < off) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + off]);
     __syncthreads();
   }
-  if (tid == 0) {
-    s.cmin[ch] = rm[0];
-    s.ccount[ch] = rc[0];
-  }
-  if (!last_to_finish(&s.ctl->sel_a_done, s.nch)) return;
-
-  // last workgroup: block time per cluster
-  const double t_end = s.ctl->t_end;
-  for (int c = tid; c < s.nc; c += kSelThreads) {
-    double m = INFINITY;
-    for (int f = s.cl_ch[c]; f < s.cl_ch[c + 1]; ++f) m = fmin(m, s.cmin[f]);
-    s.tsys[c] = (m <= t_end) ? m : -1.0;
-  }
-  __syncthreads();
-  // per-thread contiguous runs of chunks; counts of chunks at their cluster's block time
-  const int nch = s.nch;
-  const int per = (nch + kSelThreads - 1) / kSelThreads;
-  const int f0 = tid * per < nch ? tid * per : nch;
-  const int f1 = f0 + per < nch ? f0 + per : nch;
-  int64_t mine = 0;
-  for (int f = f0; f < f1; ++f) {
-    const double ts = s.tsys[s.ch_cluster[f]];
-    mine += (ts >= 0.0 && s.cmin[f] == ts) ? s.ccount[f] : 0;
-  }
-  sbuf[tid] = mine;
-  __syncthreads();
-  for (int off = 1; off < kSelThreads; off <<= 1) {
-    const int64_t add = tid >= off ? sbuf[tid - off] : 0;
-    __syncthreads();
-    sbuf[tid] += add;
-    __syncthreads();
-  }
-  int64_t base = sbuf[tid] - mine;
-  for (int f = f0; f < f1; ++f) {
-    const int c = s.ch_cluster[f];
-    const double ts = s.tsys[c];
-    const int32_t cnt = (ts >= 0.0 && s.cmin[f] == ts) ? s.ccount[f] : 0;
-    if (f == s.cl_ch[c]) s.aoff[c] = base;
-    s.ccount[f] = (int32_t)base;  // from here on: the chunk's first output slot
-    base += cnt;
-  }
-  if (tid == kSelThreads - 1) s.aoff[s.nc] = sbuf[kSelThreads - 1];
+  if (threadIdx.x == 0) s.cmin[ch] = red[0];
 }
 
-__global__ void __launch_bounds__(kSelThreads) select_b_kernel(DevState s, int64_t target_items) {
+__global__ void __launch_bounds__(kSelThreads) select2_kernel(DevState s) {
+  __shared__ double red[kSelThreads];
+  __shared__ int32_t cnt[kSelThreads];
+  const int ch = blockIdx.x;
+  const int c = s.ch_cluster[ch];
+  const int f0 = s.cl_ch[c], f1 = s.cl_ch[c + 1];
+  double mn = INFINITY;
+  for (int f = f0 + threadIdx.x; f < f1; f += kSelThreads) mn = fmin(mn, s.cmin[f]);
+  red[threadIdx.x] = mn;
+  __syncthreads();
+  for (int off = kSelThreads / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + off]);
+    __syncthreads();
+  }
+  const double tsys = red[0];
+  const bool done = !(tsys <= s.ctl->t_end);
+  int32_t count = 0;
+  if (!done) {
+    const int64_t b = s.ch_begin[ch], e = s.ch_begin[ch + 1];
+    for (int64_t i = b + threadIdx.x; i < e; i += kSelThreads) count += (s.t[i] + s.dt[i] == tsys) ? 1 : 0;
+  }
+  cnt[threadIdx.x] = count;
+  __syncthreads();
+  for (int off = kSelThreads / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off) cnt[threadIdx.x] += cnt[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    s.ccount[ch] = cnt[0];
+    if (ch == f0) s.tsys[c] = done ? -1.0 : tsys;
+  }
+}
+
+__global__ void __launch_bounds__(kSelThreads) select3_kernel(DevState s) {
   constexpr int PT = kSelChunk / kSelThreads;  // particles per thread
   __shared__ int32_t sb[kSelThreads];
+  __shared__ int64_t base_sh;
   const int ch = blockIdx.x;
   const int c = s.ch_cluster[ch];
   const int tid = threadIdx.x;
+  // active entries before this chunk (all clusters)
+  int64_t pre = 0;
+  for (int f = tid; f < ch; f += kSelThreads) pre += s.ccount[f];
+  __shared__ int64_t pbuf[kSelThreads];
+  pbuf[tid] = pre;
+  __syncthreads();
+  for (int off = kSelThreads / 2; off > 0; off >>= 1) {
+    if (tid < off) pbuf[tid] += pbuf[tid + off];
+    __syncthreads();
+  }
+  if (tid == 0) base_sh = pbuf[0];
+  __syncthreads();
+  const int64_t base = base_sh;
   const double tsys = s.tsys[c];
   const bool advancing = tsys >= 0.0;
   const int64_t b = s.ch_begin[ch], e = s.ch_begin[ch + 1];
-  if (advancing && s.cmin[ch] == tsys) {
-    const int64_t i0 = b + (int64_t)tid * PT;
-    int32_t flags = 0, mine = 0;
+  const int64_t i0 = b + (int64_t)tid * PT;
+  int32_t flags = 0, mine = 0;
+  if (advancing) {
 #pragma unroll
     for (int u = 0; u < PT; ++u) {
       const int64_t i = i0 + u;
@@ -594,30 +562,37 @@ __global__ void __launch_bounds__(kSelThreads) select_b_kernel(DevState s, int64
         ++mine;
       }
     }
-    // exclusive scan of per-thread counts (Hillis-Steele)
-    sb[tid] = mine;
+  }
+  // exclusive scan of per-thread counts (Hillis-Steele)
+  sb[tid] = mine;
+  __syncthreads();
+  for (int off = 1; off < kSelThreads; off <<= 1) {
+    const int32_t add = tid >= off ? sb[tid - off] : 0;
     __syncthreads();
-    for (int off = 1; off < kSelThreads; off <<= 1) {
-      const int32_t add = tid >= off ? sb[tid - off] : 0;
-      __syncthreads();
-      sb[tid] += add;
-      __syncthreads();
-    }
-    int64_t pos = (int64_t)s.ccount[ch] + sb[tid] - mine;
+    sb[tid] += add;
+    __syncthreads();
+  }
+  int64_t pos = base + sb[tid] - mine;
 #pragma unroll
-    for (int u = 0; u < PT; ++u)
-      if (flags & (1 << u)) s.act[pos++] = (int32_t)(i0 + u);
+  for (int u = 0; u < PT; ++u)
+    if (flags & (1 << u)) s.act[pos++] = (int32_t)(i0 + u);
+  if (tid == 0) {
+    if (ch == s.cl_ch[c]) {
+      s.aoff[c] = base;
+      if (advancing) s.tpred[c] = tsys;
+    }
+    if (ch == s.nch - 1) s.aoff[s.nc] = base + sb[kSelThreads - 1];
   }
   if (advancing) {
-    if (tid == 0 && ch == s.cl_ch[c]) s.tpred[c] = tsys;
     for (int64_t i = b + tid; i < e; i += kSelThreads) predict_one(s, i, tsys);
   }
-  if (last_to_finish(&s.ctl->sel_done, s.nch)) plan_body(s, s.aoff, s.n, target_items, 1);
 }
 
 hipError_t launch_select_plan(const DevState& s, int64_t target_items, hipStream_t st) {
-  hipLaunchKernelGGL(select_a_kernel, dim3(s.nch), dim3(kSelThreads), 0, st, s);
-  hipLaunchKernelGGL(select_b_kernel, dim3(s.nch), dim3(kSelThreads), 0, st, s, target_items);
+  hipLaunchKernelGGL(select1_kernel, dim3(s.nch), dim3(kSelThreads), 0, st, s);
+  hipLaunchKernelGGL(select2_kernel, dim3(s.nch), dim3(kSelThreads), 0, st, s);
+  hipLaunchKernelGGL(select3_kernel, dim3(s.nch), dim3(kSelThreads), 0, st, s);
+  hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(256), 0, st, s, (const int64_t*)s.aoff, s.n, target_items, 1);
   return hipGetLastError();
 }
 

@@ -179,7 +179,7 @@ def test_j_split_changes_only_rounding():
     act = icgen.active_subset(n, 900)
     ref = oracle.force(m, x, v, 1 / n, act)
     base = None
-    for target in (1, 7, 64, 2048, 100000):
+    for target in (1, 7, 64, 2048, 16384):
         sim.set_tuning(target_items=target)
         got = _gpu_force(sim, act)
         _check_fp64(got, ref)
