@@ -208,8 +208,20 @@ def run_workload(name, args):
             sim.close()
         out["config"] = f"Plummer N={n}, eps=1/N, eta=0.01, dt_max=1/8, to t={t_end}"
     elif name == "c4":
+        from paper_0711_0643_amd import tune
+
         m, x, v, coff, eps = icgen.ensemble(256, 4)
+        # layouts for this batch: tune_batch from the initial state (search timed apart)
+        probe = nb.Sim(m, x, v, eps, cluster_offsets=coff, precision=nb.MIXED)
+        w0 = time.perf_counter()
+        tuned = tune.tune_batch(probe, use_cache=False)
+        out["tune_batch"] = {"search_s": round(time.perf_counter() - w0, 2), "tuning": tuned}
+        probe.close()
         sim = nb.Sim(m, x, v, eps, cluster_offsets=coff, precision=nb.MIXED)
+        out["mixed_default_tuning"] = {k: v_ for k, v_ in drift_run(sim, 0.5, 256).items() if not k.startswith("_")}
+        sim.close()
+        sim = nb.Sim(m, x, v, eps, cluster_offsets=coff, precision=nb.MIXED)
+        sim.set_tuning(**tuned)
         rec = drift_run(sim, 0.5, 256)
         t, steps, inter = sim.progress()
         rec["block_steps_per_cluster"] = {"min": int(steps.min()), "median": int(np.median(steps)),
@@ -221,7 +233,8 @@ def run_workload(name, args):
         rec["worst_cluster"] = {"index": worst, "n": int(sizes[worst]), "drift": rec["per_cluster_drift"][worst]}
         out["mixed"] = rec
         out["config"] = (f"256 Plummer clusters, N log-uniform in [256, 8192] (sum {int(coff[-1])}), "
-                         "eps=1/N_c, mixed, to t=1/2, one graph replay = one block step of every cluster")
+                         "eps=1/N_c, mixed, to t=1/2, one graph replay = one block step of every cluster; "
+                         "'mixed' runs with the tune_batch layouts")
         sim.close()
     else:
         n = 262144

@@ -194,7 +194,8 @@ NBODY_API nbody_status nbody_get_layout(const nbody_ctx *ctx, nbody_layout *out)
  *                 1 .. 16384).
  *   min_block: smallest block size that uses, in order, the layouts with
  *              two i per lane, one i per lane, 4 lanes per i and 16 lanes
- *              per i (default 384, 192, 48, 12); smaller blocks use 64
+ *              per i (default 1024, 1024, 48, 12: the one-lane-per-i layout
+ *              is off by default); smaller blocks use 64
  *              lanes per i.  Must be non-increasing and >= 1.
  *   grid: persistent workgroups of the force launch (default: 8 per CU).
  *   mixed_format: positions of the mixed kernel as double-single FP32
@@ -205,12 +206,13 @@ NBODY_API nbody_status nbody_get_layout(const nbody_ctx *ctx, nbody_layout *out)
  *                 device at nbody_init, from the mixed kernel's sums (each
  *                 FP32 window is scaled in FP64 by 1 - 3b, potential 1 - b);
  *                 0 leaves the hardware estimate as is.
- *   near_tau: in the mixed kernel a pair whose term m_j / R^2 exceeds
- *                 near_tau * |a_i| (|a_i| from the last step) is evaluated
- *                 in FP64 (default 0.25; 0 turns this off).  One FP32 term
- *                 carries a few units of FP32 rounding, which limits the
- *                 relative force error only when that term is comparable
- *                 to the whole sum (close neighbours). */
+ *   near_tau: in the mixed kernel no pair whose term m_j / R^2 exceeds
+ *                 near_tau * |a_i| (|a_i| from the last step) is summed in
+ *                 FP32: a window of 32 j that holds one is evaluated in
+ *                 FP64 instead (default 0.25; 0 turns this off).  One FP32
+ *                 term carries a few units of FP32 rounding, which limits
+ *                 the relative force error only when that term is
+ *                 comparable to the whole sum (close neighbours). */
 typedef struct {
     int32_t target_items;
     int32_t min_block[4];

@@ -325,8 +325,8 @@ nbody_status nbody_init(nbody_ctx** out, int64_t n_total, int32_t n_clusters, co
   s.fout = (double*)(w + L.fout);
   s.status = (int32_t*)(w + L.status);
 
-  c->ctl.vmin[0] = 384;
-  c->ctl.vmin[1] = 192;
+  c->ctl.vmin[0] = 1024;
+  c->ctl.vmin[1] = 1024;
   c->ctl.vmin[2] = 48;
   c->ctl.vmin[3] = 12;
   c->ctl.near_tau = 0.25;

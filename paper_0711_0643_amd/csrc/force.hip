@@ -176,32 +176,31 @@ __device__ __forceinline__ Diff32 diff32(const typename ModeT<MODE>::I& I, const
   return d;
 }
 
-// Weight of an FP32 pair in the near-pair scheme: 1 when its term m_j / R^2
-// (= t) is below the per-i threshold g, 0 above it (the pair then goes to
-// FP64).  Branch-free: (g - t) * 2^40 clamped to [0, 1], computed as one FMA
-// from gB = g * 2^40, so the first pass and the FP64 re-scan get the same
-// weight bit for bit; the FP64 pass adds (1 - weight) of the pair, so the
-// split is exact even in the (measure-zero) fractional case.
+// Weight of an FP32 pair in the per-pair near scheme: 1 when its term
+// m_j / R^2 (= t) is below the per-i threshold g, 0 above it (the pair then
+// goes to FP64).  Branch-free: (g - t) * 2^40 clamped to [0, 1], one FMA
+// from gB = g * 2^40 and a clamp, so the first pass and the FP64 re-scan get
+// the same weight bit for bit; the re-scan adds (1 - weight) of the pair in
+// FP64, so the split is exact even in the (measure-zero) fractional case.
 constexpr float kNearScale = 1099511627776.0f;  // 2^40
 __device__ __forceinline__ float near_weight(float t, float gB) {
   return __builtin_amdgcn_fmed3f(__builtin_fmaf(-t, kNearScale, gB), 0.f, 1.f);
 }
 
 // The rest of an FP32 pair, accumulated into the FP32 window.  ZERO: drop
-// the pair when `drop` is set.  NEAR: scale it by its near-pair weight and
-// keep the smallest weight of the window in *wmin.
-template <bool ZERO, bool POT, bool NEAR>
+// the pair when `drop` is set.  WEIGHT: scale it by its near weight and keep
+// the smallest weight of the window in *wmin.
+template <bool ZERO, bool POT, bool WEIGHT>
 __device__ __forceinline__ void finish_f32(const Diff32& d, float m, bool drop, float gB, float* wmin, Acc32& A) {
   float rinv = __builtin_amdgcn_rsqf(d.r2);
   if (ZERO) rinv = drop ? 0.f : rinv;
   const float rinv2 = rinv * rinv;
   float mr, mr3;
-  if (NEAR) {
+  if (WEIGHT) {
     const float t = m * rinv2;  // m_j / R^2
     const float w = near_weight(t, gB);
     *wmin = fminf(*wmin, w);
-    const float tw = t * w;
-    mr3 = tw * rinv;
+    mr3 = (t * w) * rinv;
     mr = POT ? m * rinv * w : 0.f;
   } else {
     mr = m * rinv;
@@ -218,19 +217,19 @@ __device__ __forceinline__ void finish_f32(const Diff32& d, float m, bool drop, 
   if (POT) A.v[6] -= mr;
 }
 
-// Near-pair weight of a pair recomputed for the FP64 re-scan, with exactly
-// the operations of the first pass.
+// Near weight of a pair recomputed for the FP64 re-scan, with exactly the
+// operations of the first pass.
 __device__ __forceinline__ float near_weight_again(const Diff32& d, float m, float gB) {
   const float rinv = __builtin_amdgcn_rsqf(d.r2);
   return near_weight(m * (rinv * rinv), gB);
 }
 
-// A near pair of a mixed mode evaluated in FP64 from the same record: the
+// A pair of a mixed mode evaluated in FP64 from the same record: the
 // double-single position hi + lo is exact in FP64, velocities and mass are
 // the record's FP32 values widened.  Added straight into the FP64 totals.
 template <int MODE, bool POT>
-__device__ __forceinline__ void pair_near64(const typename ModeT<MODE>::I& I, const typename ModeT<MODE>::Rec& J,
-                                            double eps2, double share, Acc64& A) {
+__device__ __forceinline__ void pair_mixed64(const typename ModeT<MODE>::I& I, const typename ModeT<MODE>::Rec& J,
+                                             double eps2, double share, Acc64& A) {
   double dx, dy, dz;
   if constexpr (MODE == kDS) {
     dx = ((double)J.hx + (double)J.lx) - ((double)I.hx + (double)I.lx);
@@ -247,7 +246,7 @@ __device__ __forceinline__ void pair_near64(const typename ModeT<MODE>::I& I, co
   const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, __builtin_fma(dx, dx, eps2)));
   const double rinv = rsqrt_f64(r2);
   const double rinv2 = rinv * rinv;
-  const double mr = (double)J.m * rinv;
+  const double mr = share * (double)J.m * rinv;
   const double mr3 = mr * rinv2;
   const double rv = __builtin_fma(dz, dvz, __builtin_fma(dy, dvy, dx * dvx));
   const double al = (-3.0 * rinv2) * rv;
@@ -260,15 +259,53 @@ __device__ __forceinline__ void pair_near64(const typename ModeT<MODE>::I& I, co
   if (POT) A.v[6] -= mr;
 }
 
-// FP64 re-scan of one FP32 window for one i-particle: every pair whose
-// near-pair weight w is below 1 adds (1 - w) of its FP64 value.  Kept out of
-// line: it runs rarely, and inlined its FP64 temporaries would raise the
+// A window of j that may hold a near pair of particle i (cand): first the
+// exact test in FP32, m_j / R^2 > g for some pair of the window; if one is
+// found, the result is the window's FP64 sum (every pair except the dropped
+// ones: own j, padding) minus its FP32 sum B (as the caller flushed it), so
+// that adding it replaces the one by the other.  Otherwise zero.  Kept out
+// of line: it runs rarely, and inlined its FP64 temporaries would raise the
 // register count (and lower the occupancy) of the whole force kernel.
 template <int MODE, bool MASK, bool POT>
-__device__ __attribute__((noinline)) Acc64 near_window(const typename ModeT<MODE>::Rec* tile, int jl_first, int count,
-                                                       int64_t tile_j0, int64_t j_end, int64_t i_glob,
-                                                       typename ModeT<MODE>::I I, float gB, bool any, double eps2d,
-                                                       float eps2f) {
+__device__ __attribute__((noinline)) Acc64 window_f64(const typename ModeT<MODE>::Rec* tile, int jl_first, int count,
+                                                      int64_t tile_j0, int64_t j_end, int64_t i_glob,
+                                                      typename ModeT<MODE>::I I, float g, bool cand, double eps2d,
+                                                      float eps2f, Acc32 B, double ca, double cp) {
+  Acc64 R;
+#pragma unroll
+  for (int d = 0; d < 7; ++d) R.v[d] = 0.0;
+  bool hit = false;
+  if (cand) {
+    for (int u = 0; u < count; ++u) {
+      const int64_t jg = tile_j0 + jl_first + u;
+      if (MASK && (jg == i_glob || jg >= j_end)) continue;
+      const typename ModeT<MODE>::Rec J = tile[jl_first + u];
+      const float rinv = __builtin_amdgcn_rsqf(diff32<MODE>(I, J, eps2f).r2);
+      hit |= J.m * (rinv * rinv) > g;
+    }
+  }
+  if (!hit) return R;
+  // take back the window's FP32 sum, already flushed by the caller
+#pragma unroll
+  for (int d = 0; d < 6; ++d) R.v[d] = -((double)B.v[d] * ca);
+  if (POT) R.v[6] = -((double)B.v[6] * cp);
+  for (int u = 0; u < count; ++u) {
+    const int jl = jl_first + u;
+    const int64_t jg = tile_j0 + jl;
+    if (MASK && (jg == i_glob || jg >= j_end)) continue;
+    pair_mixed64<MODE, POT>(I, tile[jl], eps2d, 1.0, R);
+  }
+  return R;
+}
+
+// FP64 re-scan of one FP32 window for one i-particle in the per-pair near
+// scheme: every pair whose near weight w is below 1 adds (1 - w) of its FP64
+// value.  Out of line for the same reason as window_f64.
+template <int MODE, bool MASK, bool POT>
+__device__ __attribute__((noinline)) Acc64 near_pairs_f64(const typename ModeT<MODE>::Rec* tile, int jl_first,
+                                                          int count, int64_t tile_j0, int64_t j_end, int64_t i_glob,
+                                                          typename ModeT<MODE>::I I, float gB, bool any, double eps2d,
+                                                          float eps2f) {
   Acc64 R;
 #pragma unroll
   for (int d = 0; d < 7; ++d) R.v[d] = 0.0;
@@ -276,11 +313,10 @@ __device__ __attribute__((noinline)) Acc64 near_window(const typename ModeT<MODE
   for (int u = 0; u < count; ++u) {
     const int jl = jl_first + u;
     const int64_t jg = tile_j0 + jl;
+    if (MASK && (jg == i_glob || jg >= j_end)) continue;
     const typename ModeT<MODE>::Rec J = tile[jl];
-    const bool drop = MASK && (jg == i_glob || jg >= j_end);
-    if (drop) continue;
     const float wt = near_weight_again(diff32<MODE>(I, J, eps2f), J.m, gB);
-    if (wt < 1.f) pair_near64<MODE, POT>(I, J, eps2d, 1.0 - (double)wt, R);
+    if (wt < 1.f) pair_mixed64<MODE, POT>(I, J, eps2d, 1.0 - (double)wt, R);
   }
   return R;
 }
@@ -289,17 +325,28 @@ __device__ __attribute__((noinline)) Acc64 near_window(const typename ModeT<MODE
 // first tile-local j of the lane; PER: j per lane per tile; the global index
 // of tile entry u is tile_j0 + u.  Each j-record is read from LDS once and
 // used for all IPT particles.  MASK drops the particle's own j and entries at
-// or past j_end.  NEAR (mixed modes): pairs whose term m_j / R^2 exceeds
-// g = tau |a_i| (|a_i| from the last step) are left out of the FP32 window
-// and, after the window, evaluated in FP64 by a wave-uniform re-scan that
-// runs only when some lane met such a pair.  A single FP32 term carries a
-// few u of error, which limits the relative force only when that term is
-// comparable to the whole sum (close neighbours).
+// or past j_end.
+//
+// NEAR (mixed modes): a single FP32 term carries a few u of error, which
+// limits the relative force only when that term is comparable to the whole
+// sum, i.e. for a close neighbour with m_j / R^2 > g = tau |a_i| (|a_i| from
+// the last step).  No such pair stays in FP32; two ways to find them:
+//  * window test (layouts with one lane per i, large blocks): each lane keeps
+//    the smallest R^2 of its window (one min per pair); only when
+//    m_max / R^2_min > g (m_max: largest mass of the window's 32-entry group,
+//    wmax[]) can the window hold a near pair, and then window_f64 tests its
+//    pairs exactly and, if one is near, replaces the window's FP32 sum by its
+//    FP64 sum (a near term would also spoil the rounding of the FP32 sum).
+//  * per-pair weights (layouts that split j over lanes, small blocks, where
+//    clusters are often small and near pairs common): each pair gets weight
+//    0 or 1 in the FP32 window and near_pairs_f64 adds the weight-0 pairs in
+//    FP64.
+// Either re-scan is a wave-uniform branch taken only when some lane needs it.
 template <int MODE, int PER, int IPT, bool MASK, bool POT, bool NEAR>
-__device__ __forceinline__ void sweep_tile(const typename ModeT<MODE>::Rec* tile, int jl0,
+__device__ __forceinline__ void sweep_tile(const typename ModeT<MODE>::Rec* tile, const float* wmax, int jl0,
                                            int64_t tile_j0, int64_t j_end, const int64_t* i_glob,
-                                           const typename ModeT<MODE>::I* I, const float* gB, double eps2d,
-                                           float eps2f, double ca, double cp, Acc64* A) {
+                                           const typename ModeT<MODE>::I* I, const float* g, const float* gB,
+                                           double eps2d, float eps2f, double ca, double cp, Acc64* A) {
   if constexpr (MODE == kF64) {
 #pragma unroll 8
     for (int u = 0; u < PER; ++u) {
@@ -313,14 +360,19 @@ __device__ __forceinline__ void sweep_tile(const typename ModeT<MODE>::Rec* tile
       }
     }
   } else {
-    constexpr int F = PER < 32 ? PER : 32;  // FP32 window, then flush to FP64
+    constexpr bool WIN = NEAR && PER == kTile;  // window test
+    constexpr bool WGT = NEAR && !WIN;          // per-pair weights
+    constexpr int F = PER < 32 ? PER : 32;      // FP32 window, then flush to FP64
     for (int w = 0; w < PER; w += F) {
       Acc32 B[IPT];
-      float wmin = 1.f;  // smallest near-pair weight met by this lane in the window
+      float r2min[IPT];
+      float wmin = 1.f;  // smallest near weight met by this lane in the window
 #pragma unroll
-      for (int p = 0; p < IPT; ++p)
+      for (int p = 0; p < IPT; ++p) {
+        r2min[p] = INFINITY;
 #pragma unroll
         for (int d = 0; d < 7; ++d) B[p].v[d] = 0.f;
+      }
 #pragma unroll
       for (int u = 0; u < F; ++u) {
         const int jl = jl0 + w + u;
@@ -330,25 +382,47 @@ __device__ __forceinline__ void sweep_tile(const typename ModeT<MODE>::Rec* tile
         for (int p = 0; p < IPT; ++p) {
           const Diff32 D = diff32<MODE>(I[p], J, eps2f);
           const bool drop = MASK && (jg == i_glob[p] || jg >= j_end);
-          finish_f32<MASK, POT, NEAR>(D, J.m, drop, gB[p], &wmin, B[p]);
+          if (WIN) r2min[p] = __builtin_fminf(r2min[p], (MASK && drop) ? INFINITY : D.r2);
+          finish_f32<MASK, POT, WGT>(D, J.m, drop, gB[p], &wmin, B[p]);
         }
       }
       // flush: the FP32 window times the factor that removes the mean bias
-      // of the hardware reciprocal square root (ca for terms in R^-3, cp for R^-1)
+      // of the hardware reciprocal square root (ca for terms in R^-3, cp for
+      // R^-1)
 #pragma unroll
       for (int p = 0; p < IPT; ++p) {
 #pragma unroll
         for (int d = 0; d < 6; ++d) A[p].v[d] = __builtin_fma((double)B[p].v[d], ca, A[p].v[d]);
         if (POT) A[p].v[6] = __builtin_fma((double)B[p].v[6], cp, A[p].v[6]);
       }
-      if (NEAR && __any(wmin < 1.f)) {
-        // FP64 re-scan of the window for the pairs left out above (rare)
+      if constexpr (WIN) {
+        // windows that may hold a near pair: the exact test and, if it finds
+        // one, the window's FP64 sum in place of the FP32 one just added
+        bool cand[IPT], any_cand = false;
 #pragma unroll
         for (int p = 0; p < IPT; ++p) {
-          const Acc64 R = near_window<MODE, MASK, POT>(tile, jl0 + w, F, tile_j0, j_end, i_glob[p], I[p], gB[p],
-                                                       wmin < 1.f, eps2d, eps2f);
+          cand[p] = wmax[(jl0 + w) >> 5] > g[p] * r2min[p];
+          any_cand |= cand[p];
+        }
+        if (__any(any_cand)) {
 #pragma unroll
-          for (int d = 0; d < 7; ++d) A[p].v[d] += R.v[d];
+          for (int p = 0; p < IPT; ++p) {
+            const Acc64 R = window_f64<MODE, MASK, POT>(tile, jl0 + w, F, tile_j0, j_end, i_glob[p], I[p], g[p],
+                                                        cand[p], eps2d, eps2f, B[p], ca, cp);
+#pragma unroll
+            for (int d = 0; d < 7; ++d) A[p].v[d] += R.v[d];
+          }
+        }
+      }
+      if constexpr (WGT) {
+        if (__any(wmin < 1.f)) {  // FP64 re-scan of the pairs left out above
+#pragma unroll
+          for (int p = 0; p < IPT; ++p) {
+            const Acc64 R = near_pairs_f64<MODE, MASK, POT>(tile, jl0 + w, F, tile_j0, j_end, i_glob[p], I[p],
+                                                            gB[p], wmin < 1.f, eps2d, eps2f);
+#pragma unroll
+            for (int d = 0; d < 7; ++d) A[p].v[d] += R.v[d];
+          }
         }
       }
     }
@@ -371,7 +445,7 @@ __device__ __forceinline__ int find_cluster(const Plan* plan, int nc, int64_t it
 // the cluster's active list.
 template <int MODE, int JL, int IPT, bool POT, bool NEAR>
 __device__ void run_item(const DevState& s, const int32_t* __restrict__ act, const Plan& P, int c,
-                         int64_t local_item, unsigned char* lds) {
+                         int64_t local_item, unsigned char* lds, float* wmax) {
   static_assert(JL == 1 || IPT == 1, "several i per lane only with one lane per i");
   constexpr int SLOTS = kForceThreads / JL;  // i-slots per pass
   constexpr int IWG = SLOTS * IPT;
@@ -414,9 +488,9 @@ __device__ void run_item(const DevState& s, const int32_t* __restrict__ act, con
   const double eps2d = eps * eps;
   const float eps2f = (float)eps2d;
   const double ca = s.ctl->rsq_scale3, cp = s.ctl->rsq_scale1;
-  // near-pair threshold g = tau |a_i| (|a_i| of the last step), scaled by
-  // 2^40 for near_weight; no threshold (infinity) while |a_i| is unknown
-  float g[IPT];
+  // near-pair threshold g = tau |a_i| (|a_i| of the last step), and g * 2^40
+  // for the per-pair weights; no threshold (infinity) while |a_i| is unknown
+  float g[IPT], gB[IPT];
 #pragma unroll
   for (int p = 0; p < IPT; ++p) {
     g[p] = INFINITY;
@@ -424,8 +498,9 @@ __device__ void run_item(const DevState& s, const int32_t* __restrict__ act, con
       const int64_t n = s.n, i = i_glob[p];
       const double ax = s.a[i], ay = s.a[n + i], az = s.a[2 * n + i];
       const double gi = s.ctl->near_tau * sqrt(ax * ax + ay * ay + az * az);
-      if (gi > 0.0 && gi < 1e30) g[p] = (float)gi * kNearScale;
+      if (gi > 0.0 && gi < 1e30) g[p] = (float)gi;
     }
+    gB[p] = g[p] * kNearScale;
   }
 
   const int64_t j_begin = c_begin + (int64_t)slice * P.slice_len;
@@ -434,9 +509,17 @@ __device__ void run_item(const DevState& s, const int32_t* __restrict__ act, con
 
   for (int64_t j0 = j_begin; j0 < j_end; j0 += kTile) {
     __syncthreads();  // previous tile fully consumed
-    for (int r = tid; r < kTile; r += kForceThreads) {
-      const int64_t j = j0 + r;
-      tile[r] = (j < j_end) ? load_rec<MODE>(s, j) : zero_rec<MODE>();
+    static_assert(kTile == kForceThreads, "one record per thread");
+    {
+      const int64_t j = j0 + tid;
+      const Rec rec = (j < j_end) ? load_rec<MODE>(s, j) : zero_rec<MODE>();
+      tile[tid] = rec;
+      if (NEAR && JL == 1) {  // largest mass of each group of 32 entries (padding has m = 0)
+        float mm = (float)rec.m;
+#pragma unroll
+        for (int o = 16; o >= 1; o >>= 1) mm = fmaxf(mm, __shfl_xor(mm, o, 32));
+        if ((tid & 31) == 0) wmax[tid >> 5] = mm;
+      }
     }
     __syncthreads();
     bool mine = false;
@@ -444,10 +527,11 @@ __device__ void run_item(const DevState& s, const int32_t* __restrict__ act, con
     for (int p = 0; p < IPT; ++p) mine |= valid[p] && i_glob[p] >= j0 && i_glob[p] < j0 + kTile;
     const bool need_mask = (j0 + kTile > j_end) || __any(mine);
     if (need_mask)
-      sweep_tile<MODE, PER, IPT, true, POT, NEAR>(tile, jl * PER, j0, j_end, i_glob, I, g, eps2d, eps2f, ca, cp, A);
+      sweep_tile<MODE, PER, IPT, true, POT, NEAR>(tile, wmax, jl * PER, j0, j_end, i_glob, I, g, gB, eps2d, eps2f,
+                                                  ca, cp, A);
     else
-      sweep_tile<MODE, PER, IPT, false, POT, NEAR>(tile, jl * PER, j0, j_end, i_glob, I, g, eps2d, eps2f, ca, cp,
-                                                   A);
+      sweep_tile<MODE, PER, IPT, false, POT, NEAR>(tile, wmax, jl * PER, j0, j_end, i_glob, I, g, gB, eps2d, eps2f,
+                                                   ca, cp, A);
   }
 
   const int64_t rows_cap = s.rows_cap;
@@ -496,17 +580,18 @@ template <int MODE, bool POT, bool NEAR>
 __global__ void __launch_bounds__(kForceThreads) __attribute__((amdgpu_waves_per_eu(3)))
 force_kernel(DevState s, const int32_t* __restrict__ act) {
   __shared__ __attribute__((aligned(16))) unsigned char lds[kLdsBytes];
+  __shared__ float wmax[kTile / 32];
   const int64_t total = s.ctl->total_items;
   for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
     const int c = find_cluster(s.plan, s.nc, item);
     const Plan P = s.plan[c];
     const int64_t local = item - P.item_off;
     switch (P.variant) {
-      case 0: run_item<MODE, 1, 2, POT, NEAR>(s, act, P, c, local, lds); break;
-      case 1: run_item<MODE, 1, 1, POT, NEAR>(s, act, P, c, local, lds); break;
-      case 2: run_item<MODE, 4, 1, POT, NEAR>(s, act, P, c, local, lds); break;
-      case 3: run_item<MODE, 16, 1, POT, NEAR>(s, act, P, c, local, lds); break;
-      default: run_item<MODE, 64, 1, POT, NEAR>(s, act, P, c, local, lds); break;
+      case 0: run_item<MODE, 1, 2, POT, NEAR>(s, act, P, c, local, lds, wmax); break;
+      case 1: run_item<MODE, 1, 1, POT, NEAR>(s, act, P, c, local, lds, wmax); break;
+      case 2: run_item<MODE, 4, 1, POT, NEAR>(s, act, P, c, local, lds, wmax); break;
+      case 3: run_item<MODE, 16, 1, POT, NEAR>(s, act, P, c, local, lds, wmax); break;
+      default: run_item<MODE, 64, 1, POT, NEAR>(s, act, P, c, local, lds, wmax); break;
     }
     __syncthreads();  // LDS is reused by the next item
   }

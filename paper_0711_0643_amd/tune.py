@@ -17,9 +17,15 @@ kernel times.  Results are cached as JSON keyed by GPU architecture, HIP
 runtime version, precision and the power-of-two bucket of N; the cache file
 is $NBODY_TUNE_CACHE or ~/.cache/nbody_tune.json.
 
+For a batch of clusters, tune_batch() times whole block steps (graph
+replays) from the batch's current state instead: there the best layout
+thresholds and slicing depend on how much work every step offers across the
+whole batch, not on one cluster's block.
+
 Usage:
     sim = paper_0711_0643_amd.Sim(...)
-    cfg = tune.tune(sim)          # searches (or loads) and applies
+    cfg = tune.tune(sim)          # single cluster: searches (or loads) and applies
+    cfg = tune.tune_batch(sim)    # batch of clusters
 """
 from __future__ import annotations
 
@@ -173,6 +179,101 @@ def tune(sim, use_cache: bool = True, ladder=None, verbose: bool = False) -> dic
                 if ok and (best is None or ms < best[0]):
                     best = (ms, cfg)
     cfg = best[1] if best else tuned
+    sim.set_tuning(**cfg)
+    cfg = sim.get_tuning()
+    if use_cache:
+        cache = _load_cache()
+        cache[key] = {"tuning": cfg, "records": records}
+        _save_cache(cache)
+    return cfg
+
+
+def batch_key(sim) -> str:
+    import torch
+
+    props = torch.cuda.get_device_properties(sim.device)
+    arch = getattr(props, "gcnArchName", props.name)
+    hip = getattr(torch.version, "hip", None) or "unknown"
+    nbucket = 1 << int(math.ceil(math.log2(max(2, sim.n))))
+    prec = "mixed" if sim.params.precision == 1 else "fp64"
+    return f"{arch}|hip{hip}|{prec}|batch|Nsum{nbucket}|C{sim.nc}"
+
+
+def batch_candidates(cus: int):
+    """Layout thresholds and slicing targets searched by tune_batch."""
+    mbs = ([1024, 1024, 48, 12], [384, 192, 48, 12], [BIG, 768, 96, 12], [BIG, BIG, 48, 12], [BIG, BIG, 96, 24],
+           [BIG, BIG, 24, 6], [BIG, BIG, BIG, 12])
+    return [{"min_block": list(mb), "target_items": t} for mb in mbs for t in (8 * cus, 16 * cus)]
+
+
+def tune_batch(sim, replays: int = 200, t_end: float = None, use_cache: bool = True, verbose: bool = False) -> dict:
+    """Search (or load) min_block and target_items for a batch of clusters and apply them.
+
+    Every candidate starts from the batch's current state (restored from a
+    state blob) and is timed over `replays` block steps (HIP events on the
+    library's stream); the state is restored afterwards.  Parity gate: one
+    force pass over a fixed sample of every cluster must match the FP64
+    kernel (mixed: 1e-6 per particle; FP64: 1e-12)."""
+    import torch
+
+    key = batch_key(sim)
+    cache = _load_cache() if use_cache else {}
+    if key in cache:
+        cfg = cache[key]["tuning"]
+        sim.set_tuning(**cfg)
+        return cfg
+    log = print if verbose else (lambda *a, **k: None)
+    base = sim.get_tuning()
+    prec = sim.params.precision
+    gate = GATE_MIXED if prec == 1 else GATE_FP64
+    blob = sim.get_state()
+    dev = sim.device
+    coff = sim.cluster_offsets
+    t_now, _, _ = sim.progress()
+    if t_end is None:
+        t_end = float(np.ceil((t_now.max() + 1e-300) / sim.params.dt_max) + 1) * sim.params.dt_max
+    # gate sample: every 7th particle of every cluster
+    idx, aoff = [], [0]
+    for c in range(sim.nc):
+        sub = np.arange(int(coff[c]), int(coff[c + 1]), 7, dtype=np.int32)
+        idx.append(sub)
+        aoff.append(aoff[-1] + sub.size)
+    act = torch.as_tensor(np.concatenate(idx), device=dev)
+    aoff_t = torch.as_tensor(np.array(aoff, dtype=np.int64), device=dev)
+    sim.predict(None)
+    sim.set_precision(0)
+    sim.set_tuning(**base)
+    ref, _, _ = sim.force(act, aoff_t)
+    sim.sync()
+    ref = ref.clone()
+    sim.set_precision(prec)
+    cus = torch.cuda.get_device_properties(dev).multi_processor_count
+    records, best = [], None
+    for cand in batch_candidates(cus):
+        cfg = dict(base, **cand)
+        sim.set_state(blob)
+        sim.set_tuning(**cfg)
+        acc, _, _ = sim.force(act, aoff_t)
+        sim.sync()
+        err = _rel(acc, ref)
+        ok = err <= gate
+        ms = float("inf")
+        if ok:
+            sim.step(1, t_end)  # builds the graph for this configuration
+            sim.sync()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(sim.stream)
+            sim.step(replays, t_end)
+            e1.record(sim.stream)
+            e1.synchronize()
+            ms = e0.elapsed_time(e1) / replays
+        records.append(dict(cand, ms_per_step=ms, err=err, ok=ok))
+        log(f"batch {cand}: {ms:.4f} ms/step err {err:.2e}")
+        if ok and (best is None or ms < best[0]):
+            best = (ms, cfg)
+    sim.set_state(blob)
+    cfg = best[1] if best else base
     sim.set_tuning(**cfg)
     cfg = sim.get_tuning()
     if use_cache:

@@ -43,3 +43,42 @@ def test_tuner_picks_a_parity_passing_config(precision, tmp_path, monkeypatch):
     assert tune.tune(sim2) == cfg
     sim.close()
     sim2.close()
+
+
+def test_batch_tuner_restores_state_and_passes_parity(tmp_path, monkeypatch):
+    """tune_batch times block steps from the batch's current state: it must
+    leave that state as it found it (bitwise), return a configuration that
+    passes the parity gate, and cache it."""
+    import torch
+
+    import paper_0711_0643_amd as nb
+    from paper_0711_0643_amd import tune
+
+    monkeypatch.setenv("NBODY_TUNE_CACHE", str(tmp_path / "tune.json"))
+    m, x, v, coff, eps = icgen.ensemble(6, 12, 256, 1500)
+    banner("tune_batch 6 clusters")
+    sim = nb.Sim(m, x, v, eps, cluster_offsets=coff, precision=1)
+    sim.step(20, 0.25)
+    before = sim.host_state()
+    prog = sim.progress()
+    cfg = tune.tune_batch(sim, replays=20)
+    assert cfg == sim.get_tuning()
+    after = sim.host_state()
+    for key in before:
+        assert np.array_equal(before[key], after[key]), key
+    for u, w in zip(prog, sim.progress()):
+        assert np.array_equal(u, w)
+    data = json.loads((tmp_path / "tune.json").read_text())
+    assert data[tune.batch_key(sim)]["tuning"] == cfg
+    # the chosen configuration on the first cluster's predicted state against the oracle
+    b, e = int(coff[0]), int(coff[1])
+    act = np.arange(b, e, dtype=np.int32)
+    aoff = np.array([0] + [e - b] * len(eps), dtype=np.int64)
+    sim.predict(None)
+    a, _, _ = sim.force(act, aoff)
+    torch.cuda.synchronize()
+    xs = sim.xp.cpu().numpy()[:, b:e]
+    vs = sim.vp.cpu().numpy()[:, b:e]
+    ra, _, _ = oracle.force(m[b:e], xs, vs, eps[0])
+    assert rel_err(a.cpu().numpy(), ra).max() <= 1e-6
+    sim.close()
