@@ -28,7 +28,7 @@ constexpr uint32_t kStateVersion = 1;
 struct Layout {
   size_t coff, eps, cid, ch_cluster, ch_begin, cl_ch;
   size_t m, x, v, a, k, t, dt, xp, vp, pot, jr;
-  size_t tpred, tnow, tsys, inter, steps, cmin, ccount, act, aoff, plan, ctl, part, fout, status, eout;
+  size_t tpred, tnow, inter, steps, cm2, acount, umin, act, aoff, plan, ctl, part, fout, status, eout;
   size_t total;
   int64_t rows_cap;
   int64_t nch_max;
@@ -66,11 +66,11 @@ Layout make_layout(int64_t n, int32_t nc) {
   L.jr = take(4 * JR_ROWS * N);
   L.tpred = take(8 * C);
   L.tnow = take(8 * C);
-  L.tsys = take(8 * C);
   L.inter = take(8 * C);
   L.steps = take(8 * C);
-  L.cmin = take(8 * (size_t)L.nch_max);
-  L.ccount = take(4 * (size_t)L.nch_max);
+  L.cm2 = take(16 * (size_t)L.nch_max);
+  L.acount = take(4 * C);
+  L.umin = take(8 * N);
   L.act = take(4 * N);
   L.aoff = take(8 * (C + 1));
   L.plan = take(sizeof(Plan) * C);
@@ -116,6 +116,9 @@ struct nbody_ctx {
   int graph_mode = -1;    // force mode the graph was captured with
   int graph_pot = -1;
   bool predicted = false;
+  // the step pipeline's selection state (chunk minima, unit minima, plan)
+  // matches t, dt; cleared by every call that changes them outside the graph
+  bool sel_valid = false;
   std::vector<int64_t> coff;
   Ctl ctl{};
   bool profile = false;
@@ -170,15 +173,15 @@ void destroy_graph(nbody_ctx* c) {
   c->graph_mode = -1;
 }
 
-// One block step = select (3 kernels; the last also predicts) -> plan ->
-// force -> slice reduction with the corrector.  Captured once, replayed.
+// One block step = selection (with the predictor and the plan) -> force ->
+// slice reduction with the corrector.  Captured once, replayed.
 nbody_status build_graph(nbody_ctx* c) {
   destroy_graph(c);
   const DevState& s = c->s;
   const int mode = force_mode(c);
   if (!c->cap_stream) HIP_OK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
   HIP_OK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed));
-  hipError_t e = launch_select_plan(s, c->target_items, c->cap_stream);
+  hipError_t e = launch_select(s, c->target_items, c->cap_stream);
   if (e == hipSuccess)
     e = launch_force(s, mode, c->p.compute_pot != 0, c->ctl.near_tau > 0.0, s.act, c->grid, c->cap_stream);
   if (e == hipSuccess) e = launch_reduce_correct_step(s, c->p.compute_pot != 0, c->cap_stream);
@@ -311,11 +314,11 @@ nbody_status nbody_init(nbody_ctx** out, int64_t n_total, int32_t n_clusters, co
   s.jr = (float*)(w + L.jr);
   s.tpred = (double*)(w + L.tpred);
   s.tnow = (double*)(w + L.tnow);
-  s.tsys = (double*)(w + L.tsys);
   s.inter = (double*)(w + L.inter);
   s.steps = (int64_t*)(w + L.steps);
-  s.cmin = (double*)(w + L.cmin);
-  s.ccount = (int32_t*)(w + L.ccount);
+  s.cm2 = (double*)(w + L.cm2);
+  s.acount = (int32_t*)(w + L.acount);
+  s.umin = (double*)(w + L.umin);
   s.act = (int32_t*)(w + L.act);
   s.aoff = (int64_t*)(w + L.aoff);
   s.plan = (Plan*)(w + L.plan);
@@ -394,6 +397,7 @@ nbody_status nbody_force(nbody_ctx* c, const int32_t* active_idx, const int64_t*
   if (!active_idx || !active_offsets || !acc || !jerk) return NBODY_E_INVAL;
   if (!c->predicted) return NBODY_E_STATE;
   const DevState& s = c->s;
+  c->sel_valid = false;  // the plan is replaced
   HIP_OK(launch_plan(s, active_offsets, n_active, c->target_items, c->stream));
   std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
   if (c->profile) {
@@ -421,6 +425,7 @@ nbody_status nbody_correct(nbody_ctx* c, const int32_t* active_idx, const int64_
   if (n_active == 0) return NBODY_OK;
   if (!active_idx || !active_offsets || !acc || !jerk) return NBODY_E_INVAL;
   if (!c->predicted) return NBODY_E_STATE;
+  c->sel_valid = false;  // t and dt change
   HIP_OK(launch_correct(c->s, active_idx, active_offsets, n_active, acc, jerk, c->stream));
   return NBODY_OK;
 }
@@ -437,6 +442,10 @@ nbody_status nbody_step(nbody_ctx* c, int32_t n_block_steps, double t_end) {
     c->ctl.t_end = t_end;
     HIP_OK(hipMemcpyAsync(&c->s.ctl->t_end, &c->ctl.t_end, sizeof(double), hipMemcpyHostToDevice, c->stream));
     HIP_OK(hipStreamSynchronize(c->stream));
+  }
+  if (!c->sel_valid) {
+    HIP_OK(launch_select_init(c->s, c->stream));
+    c->sel_valid = true;
   }
   for (int32_t i = 0; i < n_block_steps; ++i) HIP_OK(hipGraphLaunch(c->gexec, c->stream));
   c->predicted = true;
@@ -456,6 +465,7 @@ nbody_status nbody_energy(nbody_ctx* c, double* E_host) {
   const DevState& s = c->s;
   HIP_OK(hipMemcpyAsync(s.tpred, s.tnow, 8 * (size_t)c->nc, hipMemcpyDeviceToDevice, c->stream));
   HIP_OK(launch_predict_all(s, c->stream));
+  c->sel_valid = false;  // the plan is replaced
   nbody_status r = force_all_internal(c, kF64);
   if (r != NBODY_OK) return r;
   double* eout = (double*)(c->ws + c->L.eout);
@@ -523,6 +533,7 @@ nbody_status nbody_set_state(nbody_ctx* c, const void* host_buf, size_t bytes) {
     o += p.bytes;
   }
   HIP_OK(hipStreamSynchronize(c->stream));
+  c->sel_valid = false;
   // the prediction no longer matches the state
   HIP_OK(hipMemcpyAsync(c->s.tpred, c->s.tnow, 8 * (size_t)c->nc, hipMemcpyDeviceToDevice, c->stream));
   HIP_OK(launch_predict_all(c->s, c->stream));

@@ -75,6 +75,9 @@ struct Ctl {
   double rsq_scale1;
   double rsq_bias;  // measured mean relative error of v_rsq_f32
   int32_t pad3[2];
+  // step pipeline (device-owned): which half of cm2 holds the current chunk
+  // minima
+  int64_t sel_parity;
 };
 
 struct DevState {
@@ -100,13 +103,13 @@ struct DevState {
   float* jr;       // [JR_ROWS][n] mixed j-records
   double* tpred;   // [nc] time of the last prediction
   double* tnow;    // [nc] time of the last block step
-  double* tsys;    // [nc] next block time (step pipeline)
   double* inter;   // [nc] pairwise interactions evaluated
   int64_t* steps;  // [nc] block steps taken
-  double* cmin;    // [nch] chunk minima of t + dt
-  int32_t* ccount; // [nch] active count per chunk
-  int32_t* act;    // [n] active list of the step pipeline
-  int64_t* aoff;   // [nc+1] active offsets of the step pipeline
+  double* cm2;     // [2][nch] per chunk: smallest t + dt of the particles the last selection left out
+  int32_t* acount; // [nc] block size of each cluster (selection counter)
+  double* umin;    // [n] per reduce unit: smallest new t + dt of the particles it corrected
+  int32_t* act;    // [n] active list (step pipeline: cluster c's block at act[coff[c]...])
+  int64_t* aoff;   // [nc+1] active offsets of the internal all-particle passes
   Plan* plan;      // [nc]
   Ctl* ctl;
   double* part;    // [7][rows_cap] partial sums

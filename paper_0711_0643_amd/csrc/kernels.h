@@ -34,8 +34,9 @@ constexpr int kReduceGrid = 2048;
 hipError_t launch_reduce(const DevState& s, const int64_t* aoff, int64_t n_active, double* acc,
                          double* jerk, double* pot, hipStream_t st);
 
-// Step pipeline: the same for the active list s.act / s.aoff built by the
-// selection, each sum handed straight to the corrector (pot: keep phi).
+// Step pipeline: the same for the active list built by the selection, each
+// sum handed straight to the corrector (pot: keep phi); records the smallest
+// new t + dt per reduce unit for the next selection.
 hipError_t launch_reduce_correct_step(const DevState& s, bool pot, hipStream_t st);
 
 // Predict every particle of every cluster to s.tpred[c] (FP64 x_p, v_p and
@@ -53,9 +54,12 @@ hipError_t launch_correct(const DevState& s, const int32_t* act, const int64_t* 
                           const double* acc, const double* jerk, hipStream_t st);
 
 
-// Block selection (three passes, the predictor fused into the last) and the
-// plan of the force pass (count_stats on).
-hipError_t launch_select_plan(const DevState& s, int64_t target_items, hipStream_t st);
+// Step pipeline: block selection with the predictor (one kernel), then the
+// plan of the force pass (count_stats on).  launch_select_init must run
+// first, and again whenever t, dt or the plan changed outside the step
+// pipeline.
+hipError_t launch_select_init(const DevState& s, hipStream_t st);
+hipError_t launch_select(const DevState& s, int64_t target_items, hipStream_t st);
 
 // Mean relative error b of the FP32 hardware reciprocal square root over
 // log-uniform arguments in [1, 4); sets ctl->rsq_scale3 = 1 - 3b and
