@@ -208,3 +208,35 @@ def test_status_reports_step_underflow():
     sim = _sim(m, x, v, 0.0, dt_min=2.0**-20)
     assert sim.status() == -5
     sim.close()
+
+
+def test_api_calls_between_steps_leave_the_run_unchanged():
+    """The step pipeline carries the next block time over from one step to
+    the next; calls that replace the plan or read the state in between
+    (force on some list, energy, predict, checkpoint) must not change the
+    trajectory: the run is bit-identical to one without them."""
+    import torch
+
+    m, x, v, coff, eps = icgen.ensemble(3, 14, 300, 900)
+    banner("api calls between steps")
+    ref = _sim(m, x, v, eps, precision=1, coff=coff)
+    ref.step(50, 0.25)
+    ref.step(50, 0.25)
+    a = ref.host_state()
+    sim = _sim(m, x, v, eps, precision=1, coff=coff)
+    sim.step(50, 0.25)
+    act = np.concatenate([np.arange(int(coff[c]), int(coff[c]) + 5, dtype=np.int32) for c in range(3)])
+    sim.force(act, np.array([0, 5, 10, 15], dtype=np.int64))
+    sim.energy()
+    sim.predict(None)
+    blob = sim.get_state()
+    sim.set_state(blob)
+    torch.cuda.synchronize()
+    sim.step(50, 0.25)
+    b = sim.host_state()
+    for key in a:
+        assert np.array_equal(a[key], b[key]), key
+    for u, w in zip(ref.progress(), sim.progress()):
+        assert np.array_equal(u, w)
+    ref.close()
+    sim.close()
