@@ -275,3 +275,60 @@ def test_mixed_near_pairs_in_fp64_fix_close_neighbours():
     assert ea_on.max() <= 1e-6
     assert ea_off.max() > ea_on.max()
     sim.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
+def test_king_salpeter_n262144_full_block_sampled(precision):
+    """King W0 = 6 with Salpeter masses, N = 262144, eps = 1/N, every
+    particle active (the largest workload, default launch configuration):
+    2048 seeded sample particles against the oracle, one by one.  Unequal
+    masses exercise the near-pair window test with a spread of m_j."""
+    n = 262144
+    m, x, v = icgen.king(n, 6.0, 5)
+    eps = 1.0 / n
+    banner(f"King+Salpeter N={n} full block precision={precision}")
+    sim = _sim(m, x, v, eps, precision)
+    got = _gpu_force(sim, np.arange(n, dtype=np.int32))
+    sample = np.sort(np.random.default_rng(3).choice(n, 2048, replace=False)).astype(np.int32)
+    ref = oracle.force(m, x, v, eps, sample)
+    part = (got[0][:, sample], got[1][:, sample], got[2][sample])
+    if precision == 0:
+        _check_fp64(part, ref)
+    else:
+        _check_mixed(part, ref, oracle.force_abs(m, x, v, eps, sample))
+    sim.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
+def test_batch_of_256_clusters_ragged_blocks(precision):
+    """The 256-cluster batch (N log-uniform in [256, 8192], sum 673038), a
+    ragged block in every cluster (1 .. N_c entries; cluster 5 has none), in
+    one force pass; 24 seeded clusters checked entry by entry against the
+    oracle run on that cluster alone."""
+    m, x, v, coff, eps = icgen.ensemble(256, 4)
+    nc = 256
+    rng = np.random.default_rng(17)
+    acts, aoff = [], [0]
+    for c in range(nc):
+        nn = int(coff[c + 1] - coff[c])
+        na = 0 if c == 5 else int(rng.integers(1, nn + 1))
+        sub = icgen.active_subset(nn, na, seed=1000 + c) + int(coff[c]) if na else np.zeros(0, np.int32)
+        acts.append(sub.astype(np.int32))
+        aoff.append(aoff[-1] + na)
+    act = np.concatenate(acts).astype(np.int32)
+    banner(f"batch of 256 clusters, {act.size} active, precision={precision}")
+    sim = _sim(m, x, v, eps, precision, coff=coff)
+    got = _gpu_force(sim, act, np.array(aoff, dtype=np.int64))
+    for c in sorted(rng.choice(nc, 24, replace=False)):
+        b, e = int(coff[c]), int(coff[c + 1])
+        s = slice(aoff[c], aoff[c + 1])
+        if aoff[c + 1] == aoff[c]:
+            continue
+        loc = acts[c] - b
+        ref = oracle.force(m[b:e], x[:, b:e], v[:, b:e], eps[c], loc)
+        part = (got[0][:, s], got[1][:, s], got[2][s])
+        if precision == 0:
+            _check_fp64(part, ref)
+        else:
+            _check_mixed(part, ref, oracle.force_abs(m[b:e], x[:, b:e], v[:, b:e], eps[c], loc))
+    sim.close()
