@@ -495,6 +495,16 @@ def main():
             "sample": f"FP64 oracle acc+jerk+pot on {n_s} active particles x {n} (same Plummer state), "
                       f"{t1 - t0:.1f} s",
         }
+        # one host thread, on a smaller sample
+        cores = oracle.threads()
+        oracle.set_threads(1)
+        one = icgen.active_subset(n, 512, seed=7)
+        t0 = time.perf_counter()
+        oracle.force(m, x, v, eps, one)
+        t2 = time.perf_counter()
+        oracle.set_threads(cores)
+        out["cpu_baseline"]["single_thread"] = {"value": round(one.size * float(n) / (t2 - t0) / 1e9, 5),
+                                                "sample": f"{one.size} active x {n}, {t2 - t0:.1f} s"}
         # both kernels against the oracle on that sample (same t = 0 state)
         ea_o = np.linalg.norm(mx["acc"][:, sample] - ra, axis=0) / np.linalg.norm(ra, axis=0)
         ef_o = np.linalg.norm(fp["acc"][:, sample] - ra, axis=0) / np.linalg.norm(ra, axis=0)

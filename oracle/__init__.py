@@ -91,6 +91,8 @@ def lib() -> ctypes.CDLL:
         L.oracle_run.restype = i64
         L.oracle_diagnostics.argtypes = [i64, p, p, p, f64, p]
         L.oracle_diagnostics.restype = None
+        L.oracle_set_threads.argtypes = [ctypes.c_int]
+        L.oracle_set_threads.restype = None
         _lib = L
     return _lib
 
@@ -98,6 +100,11 @@ def lib() -> ctypes.CDLL:
 def threads() -> int:
     """OpenMP threads the oracle's parallel loops use."""
     return int(lib().oracle_threads())
+
+
+def set_threads(n: int) -> None:
+    """Number of OpenMP threads for the oracle's parallel loops."""
+    lib().oracle_set_threads(int(n))
 
 
 def _f64(a) -> np.ndarray:

@@ -46,6 +46,9 @@
 
 /* Threads the OpenMP loops of this library use. */
 int oracle_threads(void) { return omp_get_max_threads(); }
+void oracle_set_threads(int n) {
+    if (n > 0) omp_set_num_threads(n);
+}
 
 /* ---------------------------------------------------------------------- */
 /* Pairwise sums (Sect. 2.1, Eq. Force; jerk and potential as read above). */
