@@ -93,6 +93,58 @@ __device__ __forceinline__ bool bad_range(const int64_t* aoff, const int64_t* co
   return a0 < 0 || a1 < a0 || a1 > bound || a1 - a0 > coff[c + 1] - coff[c];
 }
 
+// The plan of one cluster, apart from its offsets (items, rows, units).
+__device__ __forceinline__ void plan_row(const DevState& s, const int64_t* __restrict__ aoff, int64_t n_act_bound,
+                                         int64_t target_items, int count_stats, const int32_t* counts,
+                                         const int32_t* vmin, int c, Plan& P) {
+  const int64_t nn = s.coff[c + 1] - s.coff[c];
+  int64_t na;
+  if (counts) {
+    na = __hip_atomic_load(&counts[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  } else {
+    na = aoff[c + 1] - aoff[c];
+    if (bad_range(aoff, s.coff, c, n_act_bound)) na = 0;
+  }
+  int var = kNumVariants - 1;
+  for (int vv = kNumVariants - 2; vv >= 0; --vv)
+    if (na >= vmin[vv]) var = vv;
+  const int64_t iwg = variant_iwg(var);
+  const int64_t chunks = (na + iwg - 1) / iwg;
+  int64_t S = 1;
+  if (chunks > 0) {
+    const int64_t smax_tiles = (nn + kTile - 1) / kTile;
+    const int64_t smax_rows = (kRowsPerParticle * nn + kRowsPerCluster) / na;
+    S = (target_items + chunks - 1) / chunks;
+    if (S > smax_tiles) S = smax_tiles;
+    if (S > smax_rows) S = smax_rows;
+    if (S < 1) S = 1;
+  }
+  int64_t slen = (nn + S - 1) / S;
+  slen = (slen + kTile - 1) / kTile * kTile;
+  S = (nn + slen - 1) / slen;
+  P.n_act = (int32_t)na;
+  P.variant = var;
+  P.chunks = (int32_t)chunks;
+  P.slices = (int32_t)S;
+  P.slice_len = (int32_t)slen;
+  int tp = 1;
+  while (tp < S && tp < 256) tp <<= 1;
+  P.red_tp = tp;
+  if (count_stats && na > 0) {  // block-step counters (one writer per cluster)
+    s.inter[c] += (double)na * (double)nn;
+    s.steps[c] += 1;
+  }
+  if (counts) {
+    P.act_off = s.coff[c];
+  } else {  // clamped so that a corrupt offset cannot steer reads out of the list
+    P.act_off = aoff[c] < 0 ? 0 : aoff[c] > n_act_bound ? n_act_bound : aoff[c];
+  }
+}
+
+__device__ __forceinline__ int64_t plan_units(const Plan& P) {
+  return (P.n_act + (256 / P.red_tp) - 1) / (256 / P.red_tp);
+}
+
 // The plan, computed by one workgroup of 256 threads.
 // counts != NULL (step pipeline): cluster c's block is counts[c] entries of
 // the active list starting at coff[c] (its own segment); aoff is unused.
@@ -104,7 +156,9 @@ __device__ void plan_body(const DevState& s, const int64_t* __restrict__ aoff, i
   const int per = (nc + 255) / 256;
   const int c0 = tid * per < nc ? tid * per : nc;
   const int c1 = c0 + per < nc ? c0 + per : nc;
-  const Ctl ctl = *s.ctl;
+  int32_t vmin[kNumVariants - 1];
+#pragma unroll
+  for (int v = 0; v < kNumVariants - 1; ++v) vmin[v] = s.ctl->vmin[v];
 
   if (!counts) {
     bool bad = (tid == 0) && (aoff[0] != 0);
@@ -115,52 +169,12 @@ __device__ void plan_body(const DevState& s, const int64_t* __restrict__ aoff, i
 
   int64_t my_items = 0, my_rows = 0, my_red = 0;
   for (int c = c0; c < c1; ++c) {
-    const int64_t nn = s.coff[c + 1] - s.coff[c];
-    int64_t na;
-    if (counts) {
-      na = __hip_atomic_load(&counts[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      na = aoff[c + 1] - aoff[c];
-      if (bad_range(aoff, s.coff, c, n_act_bound)) na = 0;
-    }
-    int var = kNumVariants - 1;
-    for (int vv = kNumVariants - 2; vv >= 0; --vv)
-      if (na >= ctl.vmin[vv]) var = vv;
-    const int64_t iwg = variant_iwg(var);
-    const int64_t chunks = (na + iwg - 1) / iwg;
-    int64_t S = 1;
-    if (chunks > 0) {
-      const int64_t smax_tiles = (nn + kTile - 1) / kTile;
-      const int64_t smax_rows = (kRowsPerParticle * nn + kRowsPerCluster) / na;
-      S = (target_items + chunks - 1) / chunks;
-      if (S > smax_tiles) S = smax_tiles;
-      if (S > smax_rows) S = smax_rows;
-      if (S < 1) S = 1;
-    }
-    int64_t slen = (nn + S - 1) / S;
-    slen = (slen + kTile - 1) / kTile * kTile;
-    S = (nn + slen - 1) / slen;
     Plan& P = s.plan[c];
-    P.n_act = (int32_t)na;
-    P.variant = var;
-    P.chunks = (int32_t)chunks;
-    P.slices = (int32_t)S;
-    P.slice_len = (int32_t)slen;
-    int tp = 1;
-    while (tp < S && tp < 256) tp <<= 1;
-    P.red_tp = tp;
-    if (count_stats && na > 0) {  // block-step counters (one writer per cluster)
-      s.inter[c] += (double)na * (double)nn;
-      s.steps[c] += 1;
-    }
-    if (counts) {
-      P.act_off = s.coff[c];
-    } else {  // clamped so that a corrupt offset cannot steer reads out of the list
-      P.act_off = aoff[c] < 0 ? 0 : aoff[c] > n_act_bound ? n_act_bound : aoff[c];
-    }
+    plan_row(s, aoff, n_act_bound, target_items, count_stats, counts, vmin, c, P);
+    const int64_t chunks = P.chunks, S = P.slices, na = P.n_act;
     my_items += chunks * S;
     my_rows += S * na;
-    my_red += (na + (256 / tp) - 1) / (256 / tp);
+    my_red += plan_units(P);
   }
   __syncthreads();
   int64_t tot_items, tot_rows, tot_red;
@@ -174,7 +188,7 @@ __device__ void plan_body(const DevState& s, const int64_t* __restrict__ aoff, i
     P.red_off = bu;
     bi += (int64_t)P.chunks * P.slices;
     br += (int64_t)P.slices * P.n_act;
-    bu += (P.n_act + (256 / P.red_tp) - 1) / (256 / P.red_tp);
+    bu += plan_units(P);
   }
   if (tid == 0) {
     if (tot_rows > s.rows_cap) {  // cannot happen with the bounds of the plan; refuse the pass
@@ -188,6 +202,61 @@ __device__ void plan_body(const DevState& s, const int64_t* __restrict__ aoff, i
   }
 }
 
+// The plan for at most 64 clusters: one wave, one cluster per lane, the
+// offsets by wave shuffles (no barriers).
+__device__ __forceinline__ int64_t wave_exclusive_scan(int64_t v, int64_t* total) {
+  const int lane = threadIdx.x;
+  int64_t x = v;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int64_t y = __shfl_up(x, off);
+    if (lane >= off) x += y;
+  }
+  *total = __shfl(x, 63);
+  return x - v;
+}
+
+__device__ void plan_small(const DevState& s, const int64_t* __restrict__ aoff, int64_t n_act_bound,
+                           int64_t target_items, int count_stats, const int32_t* counts) {
+  const int c = threadIdx.x;
+  const int nc = s.nc;
+  int32_t vmin[kNumVariants - 1];
+#pragma unroll
+  for (int v = 0; v < kNumVariants - 1; ++v) vmin[v] = s.ctl->vmin[v];
+  if (!counts) {
+    bool bad = (c == 0) && (aoff[0] != 0);
+    if (c < nc && bad_range(aoff, s.coff, c, n_act_bound)) bad = true;
+    if (bad) set_status(s, ST_INDEX);
+  }
+  Plan P{};
+  if (c < nc) plan_row(s, aoff, n_act_bound, target_items, count_stats, counts, vmin, c, P);
+  int64_t tot_items, tot_rows, tot_red;
+  P.item_off = wave_exclusive_scan(c < nc ? (int64_t)P.chunks * P.slices : 0, &tot_items);
+  P.slot_base = wave_exclusive_scan(c < nc ? (int64_t)P.slices * P.n_act : 0, &tot_rows);
+  P.red_off = wave_exclusive_scan(c < nc ? plan_units(P) : 0, &tot_red);
+  if (c < nc) s.plan[c] = P;
+  if (c == 0) {
+    if (tot_rows > s.rows_cap) {  // cannot happen with the bounds of the plan; refuse the pass
+      set_status(s, ST_INDEX);
+      tot_items = 0;
+      tot_red = 0;
+    }
+    s.ctl->total_items = tot_items;
+    s.ctl->total_rows = tot_rows;
+    s.ctl->total_red = tot_red;
+  }
+}
+
+__global__ void __launch_bounds__(64) plan_small_kernel(DevState s, const int64_t* __restrict__ aoff,
+                                                        int64_t n_act_bound, int64_t target_items, int count_stats,
+                                                        const int32_t* counts) {
+  plan_small(s, aoff, n_act_bound, target_items, count_stats, counts);
+  if (counts) {  // step pipeline: hand the counters and the cm2 half on to the next step
+    if ((int)threadIdx.x < s.nc) s.acount[threadIdx.x] = 0;
+    if (threadIdx.x == 0) s.ctl->sel_parity += 1;
+  }
+}
+
 __global__ void __launch_bounds__(256) plan_kernel(DevState s, const int64_t* __restrict__ aoff,
                                                    int64_t n_act_bound, int64_t target_items, int count_stats) {
   plan_body(s, aoff, n_act_bound, target_items, count_stats, nullptr);
@@ -195,7 +264,11 @@ __global__ void __launch_bounds__(256) plan_kernel(DevState s, const int64_t* __
 
 hipError_t launch_plan(const DevState& s, const int64_t* aoff, int64_t n_act_bound, int64_t target_items,
                        hipStream_t st, int count_stats) {
-  hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(256), 0, st, s, aoff, n_act_bound, target_items, count_stats);
+  if (s.nc <= 64)
+    hipLaunchKernelGGL(plan_small_kernel, dim3(1), dim3(64), 0, st, s, aoff, n_act_bound, target_items, count_stats,
+                       (const int32_t*)nullptr);
+  else
+    hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(256), 0, st, s, aoff, n_act_bound, target_items, count_stats);
   return hipGetLastError();
 }
 
@@ -631,7 +704,11 @@ hipError_t launch_select_init(const DevState& s, hipStream_t st) {
 
 hipError_t launch_select(const DevState& s, int64_t target_items, hipStream_t st) {
   hipLaunchKernelGGL(select_kernel, dim3(s.nch), dim3(kSelThreads), 0, st, s);
-  hipLaunchKernelGGL(plan_step_kernel, dim3(1), dim3(256), 0, st, s, target_items);
+  if (s.nc <= 64)
+    hipLaunchKernelGGL(plan_small_kernel, dim3(1), dim3(64), 0, st, s, (const int64_t*)nullptr, s.n, target_items,
+                       1, (const int32_t*)s.acount);
+  else
+    hipLaunchKernelGGL(plan_step_kernel, dim3(1), dim3(256), 0, st, s, target_items);
   return hipGetLastError();
 }
 
