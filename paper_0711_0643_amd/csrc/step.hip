@@ -73,19 +73,27 @@ hipError_t launch_identity(const DevState& s, hipStream_t st) {
 // the partial-row budget of the cluster allows.  Offsets of items and
 // partial rows are exclusive prefix sums in cluster order.
 __device__ __forceinline__ int64_t wg_exclusive_scan(int64_t v, int64_t* buf, int64_t* total) {
-  const int tid = threadIdx.x;
-  buf[tid] = v;
-  __syncthreads();
-  for (int off = 1; off < 256; off <<= 1) {
-    const int64_t add = tid >= off ? buf[tid - off] : 0;
-    __syncthreads();
-    buf[tid] += add;
-    __syncthreads();
+  // 256 threads: inclusive scan inside each wave by shuffles, then the wave
+  // totals through LDS (buf[0..3])
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  int64_t x = v;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int64_t y = __shfl_up(x, off);
+    if (lane >= off) x += y;
   }
-  const int64_t incl = buf[tid];
-  *total = buf[255];
+  if (lane == 63) buf[wave] = x;
   __syncthreads();
-  return incl - v;
+  int64_t before = 0, all = 0;
+#pragma unroll
+  for (int w = 0; w < 4; ++w) {
+    const int64_t t = buf[w];
+    before += w < wave ? t : 0;
+    all += t;
+  }
+  *total = all;
+  __syncthreads();  // buf is reused by the next scan
+  return before + x - v;
 }
 
 __device__ __forceinline__ bool bad_range(const int64_t* aoff, const int64_t* coff, int c, int64_t bound) {
@@ -623,7 +631,7 @@ __global__ void __launch_bounds__(kSelThreads) select_init_kernel(DevState s) {
 __global__ void __launch_bounds__(kSelThreads) select_kernel(DevState s) {
   constexpr int PT = kSelChunk / kSelThreads;  // particles per thread
   __shared__ double buf[kSelThreads / 64];
-  __shared__ int32_t sb[kSelThreads];
+  __shared__ int64_t sbuf[kSelThreads / 64];
   __shared__ int64_t base_sh;
   const int ch = blockIdx.x;
   const int c = s.ch_cluster[ch];
@@ -663,23 +671,16 @@ __global__ void __launch_bounds__(kSelThreads) select_kernel(DevState s) {
     }
   }
   rest = block_min(rest, buf);
-  // inclusive scan of the per-thread counts (Hillis-Steele)
-  sb[tid] = mine;
-  __syncthreads();
-  for (int off = 1; off < kSelThreads; off <<= 1) {
-    const int32_t add = tid >= off ? sb[tid - off] : 0;
-    __syncthreads();
-    sb[tid] += add;
-    __syncthreads();
-  }
+  // exclusive scan of the per-thread counts
+  int64_t total;
+  const int64_t before = wg_exclusive_scan(mine, sbuf, &total);
   if (tid == 0) {
     nxt[ch] = rest;
-    const int32_t total = sb[kSelThreads - 1];
-    base_sh = total > 0 ? atomicAdd(&s.acount[c], total) : 0;
+    base_sh = total > 0 ? atomicAdd(&s.acount[c], (int32_t)total) : 0;
     if (advancing && ch == s.cl_ch[c]) s.tpred[c] = tsys;
   }
   __syncthreads();
-  int64_t pos = s.coff[c] + base_sh + sb[tid] - mine;
+  int64_t pos = s.coff[c] + base_sh + before;
 #pragma unroll
   for (int u = 0; u < PT; ++u)
     if (flags & (1 << u)) s.act[pos++] = (int32_t)(i0 + u);
