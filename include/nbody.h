@@ -160,6 +160,15 @@ NBODY_API nbody_status nbody_sync(nbody_ctx *ctx);
  * particle of a cluster is at the same time (multiples of dt_max). */
 NBODY_API nbody_status nbody_energy(nbody_ctx *ctx, double *E_host);
 
+/* Per-cluster diagnostics (Sect. 2.1, diagnostic output), FP64, written to
+ * out_host[8 * c + k] for k = 0 kinetic energy sum m v^2/2, 1 potential
+ * energy (1/2) sum m phi (softened, self pair excluded, phi from an FP64
+ * force pass on every particle), 2..4 momentum sum m v, 5..7 angular
+ * momentum sum m x cross v.  Evaluated on the state predicted to each
+ * cluster's time (x, v themselves when every particle is at that time).
+ * Synchronous; out_host holds 8 * n_clusters doubles. */
+NBODY_API nbody_status nbody_diagnostics(nbody_ctx *ctx, double *out_host);
+
 /* Per-cluster progress, synchronous: time of the last block step, number of
  * block steps taken and pairwise interactions evaluated (block size times
  * cluster size, summed).  Any pointer may be NULL. */

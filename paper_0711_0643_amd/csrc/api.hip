@@ -78,7 +78,7 @@ Layout make_layout(int64_t n, int32_t nc) {
   L.part = take(8 * 7 * (size_t)L.rows_cap);
   L.fout = take(8 * 7 * N);
   L.status = take(4);
-  L.eout = take(8 * C);
+  L.eout = take(64 * C);
   L.total = o;
   return L;
 }
@@ -460,8 +460,8 @@ nbody_status nbody_sync(nbody_ctx* c) {
   return status_from_bits(bits);
 }
 
-nbody_status nbody_energy(nbody_ctx* c, double* E_host) {
-  if (!c || !E_host) return NBODY_E_INVAL;
+nbody_status nbody_diagnostics(nbody_ctx* c, double* out_host) {
+  if (!c || !out_host) return NBODY_E_INVAL;
   const DevState& s = c->s;
   HIP_OK(hipMemcpyAsync(s.tpred, s.tnow, 8 * (size_t)c->nc, hipMemcpyDeviceToDevice, c->stream));
   HIP_OK(launch_predict_all(s, c->stream));
@@ -469,11 +469,20 @@ nbody_status nbody_energy(nbody_ctx* c, double* E_host) {
   nbody_status r = force_all_internal(c, kF64);
   if (r != NBODY_OK) return r;
   double* eout = (double*)(c->ws + c->L.eout);
-  HIP_OK(launch_energy(s, eout, c->stream));
-  HIP_OK(hipMemcpyAsync(E_host, eout, 8 * (size_t)c->nc, hipMemcpyDeviceToHost, c->stream));
+  HIP_OK(launch_diag(s, eout, c->stream));
+  HIP_OK(hipMemcpyAsync(out_host, eout, 64 * (size_t)c->nc, hipMemcpyDeviceToHost, c->stream));
   HIP_OK(hipStreamSynchronize(c->stream));
   c->predicted = true;
   return nbody_sync(c);
+}
+
+nbody_status nbody_energy(nbody_ctx* c, double* E_host) {
+  if (!c || !E_host) return NBODY_E_INVAL;
+  std::vector<double> d(8 * (size_t)c->nc);
+  const nbody_status r = nbody_diagnostics(c, d.data());
+  if (r != NBODY_OK) return r;
+  for (int i = 0; i < c->nc; ++i) E_host[i] = d[8 * (size_t)i] + d[8 * (size_t)i + 1];
+  return NBODY_OK;
 }
 
 nbody_status nbody_progress(nbody_ctx* c, double* t_host, int64_t* steps_host, double* inter_host) {

@@ -66,7 +66,9 @@ hipError_t launch_select(const DevState& s, int64_t target_items, hipStream_t st
 // ctl->rsq_scale1 = 1 - b (or both to 1 when correct == 0).
 hipError_t launch_rsq_bias(const DevState& s, int correct, hipStream_t st);
 
-// Per-cluster energy from s.fout's potential row (identity active list).
-hipError_t launch_energy(const DevState& s, double* e_out, hipStream_t st);
+// Per-cluster diagnostics (8 per cluster: kinetic and potential energy,
+// momentum, angular momentum) from the predicted state and s.fout's
+// potential row (identity active list).
+hipError_t launch_diag(const DevState& s, double* out, hipStream_t st);
 
 }  // namespace nb

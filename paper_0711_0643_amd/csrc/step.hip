@@ -755,27 +755,48 @@ hipError_t launch_rsq_bias(const DevState& s, int correct, hipStream_t st) {
 // ---------------------------------------------------------------------------
 // Per-cluster softened energy, E = sum m v^2 / 2 + (1/2) sum m phi, from the
 // potential row of s.fout (identity active list).  Fixed-order sums.
-__global__ void __launch_bounds__(256) energy_kernel(DevState s, double* e_out) {
-  __shared__ double red[256];
-  const int c = blockIdx.x;
+// Per-cluster diagnostics at the prediction time (Sect. 2.1, diagnostic
+// output), FP64, one workgroup per cluster: out[8 c + ...] = kinetic energy
+// sum m v^2 / 2, potential energy (1/2) sum m phi (phi from s.fout's
+// potential row, self pair excluded), momentum sum m v (3), angular momentum
+// sum m x cross v (3).  Positions and velocities are the predicted ones
+// (equal to x, v when every particle is at the cluster's time).
+__global__ void __launch_bounds__(256) diag_kernel(DevState s, double* out) {
+  __shared__ double red[8][256];
+  const int c = blockIdx.x, tid = threadIdx.x;
   const int64_t n = s.n;
   const int64_t b = s.coff[c], e = s.coff[c + 1];
-  double acc = 0.0;
-  for (int64_t i = b + threadIdx.x; i < e; i += 256) {
-    const double vx = s.v[i], vy = s.v[n + i], vz = s.v[2 * n + i];
-    acc += 0.5 * s.m[i] * (vx * vx + vy * vy + vz * vz) + 0.5 * s.m[i] * s.fout[6 * n + i];
+  double acc[8];
+#pragma unroll
+  for (int d = 0; d < 8; ++d) acc[d] = 0.0;
+  for (int64_t i = b + tid; i < e; i += 256) {
+    const double m = s.m[i];
+    const double x = s.xp[i], y = s.xp[n + i], z = s.xp[2 * n + i];
+    const double vx = s.vp[i], vy = s.vp[n + i], vz = s.vp[2 * n + i];
+    acc[0] += 0.5 * m * (vx * vx + vy * vy + vz * vz);
+    acc[1] += 0.5 * m * s.fout[6 * n + i];
+    acc[2] += m * vx;
+    acc[3] += m * vy;
+    acc[4] += m * vz;
+    acc[5] += m * (y * vz - z * vy);
+    acc[6] += m * (z * vx - x * vz);
+    acc[7] += m * (x * vy - y * vx);
   }
-  red[threadIdx.x] = acc;
+#pragma unroll
+  for (int d = 0; d < 8; ++d) red[d][tid] = acc[d];
   __syncthreads();
   for (int off = 128; off > 0; off >>= 1) {
-    if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    if (tid < off) {
+#pragma unroll
+      for (int d = 0; d < 8; ++d) red[d][tid] += red[d][tid + off];
+    }
     __syncthreads();
   }
-  if (threadIdx.x == 0) e_out[c] = red[0];
+  if (tid < 8) out[8 * c + tid] = red[tid][0];
 }
 
-hipError_t launch_energy(const DevState& s, double* e_out, hipStream_t st) {
-  hipLaunchKernelGGL(energy_kernel, dim3(s.nc), dim3(256), 0, st, s, e_out);
+hipError_t launch_diag(const DevState& s, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(diag_kernel, dim3(s.nc), dim3(256), 0, st, s, out);
   return hipGetLastError();
 }
 

@@ -41,6 +41,7 @@ EXPORTED = [
     "nbody_step",
     "nbody_sync",
     "nbody_energy",
+    "nbody_diagnostics",
     "nbody_progress",
     "nbody_state_bytes",
     "nbody_get_state",
@@ -145,6 +146,8 @@ def lib() -> ctypes.CDLL:
         L.nbody_sync.restype = st
         L.nbody_energy.argtypes = [p, p]
         L.nbody_energy.restype = st
+        L.nbody_diagnostics.argtypes = [p, p]
+        L.nbody_diagnostics.restype = st
         L.nbody_progress.argtypes = [p, p, p, p]
         L.nbody_progress.restype = st
         L.nbody_state_bytes.argtypes = [p, ctypes.POINTER(sz)]
@@ -377,6 +380,14 @@ class Sim:
         e = np.zeros(self.nc)
         _check(lib().nbody_energy(self._ctx, e.ctypes.data), "nbody_energy")
         return e
+
+    def diagnostics(self) -> dict:
+        """Per cluster: kinetic, potential and total energy, momentum (nc, 3),
+        angular momentum (nc, 3)."""
+        d = np.zeros((self.nc, 8))
+        _check(lib().nbody_diagnostics(self._ctx, d.ctypes.data), "nbody_diagnostics")
+        return {"KE": d[:, 0].copy(), "PE": d[:, 1].copy(), "E": d[:, 0] + d[:, 1], "P": d[:, 2:5].copy(),
+                "L": d[:, 5:8].copy()}
 
     def progress(self):
         t = np.zeros(self.nc)

@@ -240,3 +240,27 @@ def test_api_calls_between_steps_leave_the_run_unchanged():
         assert np.array_equal(u, w)
     ref.close()
     sim.close()
+
+
+def test_diagnostics_match_oracle():
+    """Kinetic and potential energy, momentum and angular momentum of every
+    cluster at a synchronised time against the oracle's diagnostics of the
+    same state."""
+    m, x, v, coff, eps = icgen.ensemble(3, 21, 300, 1200)
+    banner("diagnostics")
+    sim = _sim(m, x, v, eps, precision=1, coff=coff)
+    sim.run(0.125, chunk=128)
+    d = sim.diagnostics()
+    st = sim.host_state()
+    assert np.all(st["t"] == 0.125)
+    for c in range(3):
+        b, e = int(coff[c]), int(coff[c + 1])
+        ref = oracle.diagnostics(m[b:e], st["x"][:, b:e], st["v"][:, b:e], eps[c])
+        for key in ("KE", "PE", "E"):
+            assert abs(d[key][c] - ref[key]) <= 1e-13 * abs(ref[key]), (c, key, d[key][c], ref[key])
+        scale_p = float(np.sum(m[b:e] * np.linalg.norm(st["v"][:, b:e], axis=0)))
+        scale_l = float(np.sum(m[b:e] * np.linalg.norm(st["x"][:, b:e], axis=0) * np.linalg.norm(st["v"][:, b:e], axis=0)))
+        assert np.max(np.abs(d["P"][c] - ref["P"])) <= 1e-14 * scale_p
+        assert np.max(np.abs(d["L"][c] - ref["L"])) <= 1e-14 * scale_l
+    assert np.allclose(sim.energy(), d["E"], rtol=0, atol=0)
+    sim.close()
