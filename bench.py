@@ -174,20 +174,33 @@ def run_workload(name, args):
     import paper_0711_0643_amd as nb
 
     def drift_run(sim, t_end, chunk):
-        E0 = sim.energy()
+        d0 = sim.diagnostics()
+        E0 = d0["E"]
         torch.cuda.synchronize()
         w0 = time.perf_counter()
         sim.run(t_end, chunk=chunk)
         torch.cuda.synchronize()
         wall = time.perf_counter() - w0
-        E1 = sim.energy()
+        d1 = sim.diagnostics()
+        E1 = d1["E"]
         t, steps, inter = sim.progress()
         drift = (E1 - E0) / np.abs(E0)
+        # momentum and angular momentum change, relative to sum m |v| and sum m |x||v| at the start
+        st = sim.host_state()
+        sc_p, sc_l = [], []
+        for c in range(sim.nc):
+            b, e = int(sim.cluster_offsets[c]), int(sim.cluster_offsets[c + 1])
+            mv = st["m"][b:e] * np.linalg.norm(st["v"][:, b:e], axis=0)
+            sc_p.append(mv.sum())
+            sc_l.append((mv * np.linalg.norm(st["x"][:, b:e], axis=0)).sum())
+        dP = float(np.max(np.linalg.norm(d1["P"] - d0["P"], axis=1) / np.array(sc_p)))
+        dL = float(np.max(np.linalg.norm(d1["L"] - d0["L"], axis=1) / np.array(sc_l)))
         return {"_drift": drift, "wall_s": round(wall, 4), "block_steps": [int(x) for x in steps][:4] if steps.size > 4 else
                 [int(x) for x in steps], "interactions": float(inter.sum()),
                 "Ginteractions_per_s": round(float(inter.sum()) / wall / 1e9, 3),
                 "mean_block": float(inter.sum() / max(1, steps.sum())) / float(sim.n / sim.nc),
                 "max_abs_rel_energy_drift": float(np.abs(drift).max()),
+                "max_rel_momentum_change": dP, "max_rel_angular_momentum_change": dL,
                 "rel_energy_drift": [float(d) for d in drift[:4]], "t_end": t_end}
 
     out = {"workload": name}
