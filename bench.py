@@ -465,11 +465,9 @@ def main():
             "interactions_per_launch": inter_step,
             "kernel_ms": round(mx["kernel_s"] * 1e3, 4),
             # labelled context, not used for frac: the 60-flop acc+jerk count common in
-            # the GPU Hermite literature, and the FP32 peak without packed math (the
-            # build compiles with packed FP32 instructions disabled)
+            # the GPU Hermite literature
             "context": {
                 "frac_at_60_flops_per_interaction": round(60 * inter_step / mx["kernel_s"] / 1e12 / PEAK_FP32_TFLOPS, 4),
-                "frac_of_unpacked_fp32_peak": round(achieved / (PEAK_FP32_TFLOPS / 2), 4),
             },
         },
         "fp64": {
