@@ -116,6 +116,10 @@ struct nbody_ctx {
   int graph_mode = -1;    // force mode the graph was captured with
   int graph_pot = -1;
   bool predicted = false;
+  // the predicted state holds every field (x_p, v_p, all j-record rows) for
+  // every particle: true after a full prediction, false after block steps,
+  // whose predictor writes only what the step's force and corrector read
+  bool pred_full = false;
   // the step pipeline's selection state (chunk minima, unit minima, plan)
   // matches t, dt; cleared by every call that changes them outside the graph
   bool sel_valid = false;
@@ -181,7 +185,7 @@ nbody_status build_graph(nbody_ctx* c) {
   const int mode = force_mode(c);
   if (!c->cap_stream) HIP_OK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
   HIP_OK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed));
-  hipError_t e = launch_select(s, c->target_items, c->cap_stream);
+  hipError_t e = launch_select(s, c->target_items, mode, c->cap_stream);
   if (e == hipSuccess)
     e = launch_force(s, mode, c->p.compute_pot != 0, c->ctl.near_tau > 0.0, s.act, c->grid, c->cap_stream);
   if (e == hipSuccess) e = launch_reduce_correct_step(s, c->p.compute_pot != 0, c->cap_stream);
@@ -356,6 +360,7 @@ nbody_status nbody_init(nbody_ctx** out, int64_t n_total, int32_t n_clusters, co
   if (r == NBODY_OK && launch_rsq_bias(s, c->rsq_correct, st) != hipSuccess) r = NBODY_E_HIP;
   // start-up (Sect. 2.1): a, k of every particle at t = 0, then initial steps
   if (r == NBODY_OK && launch_predict_all(s, st) != hipSuccess) r = NBODY_E_HIP;  // tpred = 0: x_p = x
+  c->pred_full = true;
   // the start-up pass is FP64 in every precision: one N^2 pass, and its |a|
   // is what the mixed kernel's near-pair test reads at the first step
   if (r == NBODY_OK) r = force_all_internal(c, kF64);
@@ -387,6 +392,19 @@ nbody_status nbody_predict(nbody_ctx* c, const double* t_pred) {
   }
   HIP_OK(launch_predict_all(c->s, c->stream));
   c->predicted = true;
+  c->pred_full = true;
+  return NBODY_OK;
+}
+
+// After block steps the predicted state is partial and the corrected
+// particles' entries are from before their correction: predict every
+// particle again to each cluster's time before a direct force or corrector
+// call reads it.
+nbody_status complete_prediction(nbody_ctx* c) {
+  if (!c->pred_full) {
+    HIP_OK(launch_predict_all(c->s, c->stream));
+    c->pred_full = true;
+  }
   return NBODY_OK;
 }
 
@@ -397,6 +415,8 @@ nbody_status nbody_force(nbody_ctx* c, const int32_t* active_idx, const int64_t*
   if (!active_idx || !active_offsets || !acc || !jerk) return NBODY_E_INVAL;
   if (!c->predicted) return NBODY_E_STATE;
   const DevState& s = c->s;
+  const nbody_status r = complete_prediction(c);
+  if (r != NBODY_OK) return r;
   c->sel_valid = false;  // the plan is replaced
   HIP_OK(launch_plan(s, active_offsets, n_active, c->target_items, c->stream));
   std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
@@ -425,6 +445,8 @@ nbody_status nbody_correct(nbody_ctx* c, const int32_t* active_idx, const int64_
   if (n_active == 0) return NBODY_OK;
   if (!active_idx || !active_offsets || !acc || !jerk) return NBODY_E_INVAL;
   if (!c->predicted) return NBODY_E_STATE;
+  const nbody_status r = complete_prediction(c);
+  if (r != NBODY_OK) return r;
   c->sel_valid = false;  // t and dt change
   HIP_OK(launch_correct(c->s, active_idx, active_offsets, n_active, acc, jerk, c->stream));
   return NBODY_OK;
@@ -449,6 +471,7 @@ nbody_status nbody_step(nbody_ctx* c, int32_t n_block_steps, double t_end) {
   }
   for (int32_t i = 0; i < n_block_steps; ++i) HIP_OK(hipGraphLaunch(c->gexec, c->stream));
   c->predicted = true;
+  c->pred_full = false;
   return NBODY_OK;
 }
 
@@ -465,6 +488,7 @@ nbody_status nbody_diagnostics(nbody_ctx* c, double* out_host) {
   const DevState& s = c->s;
   HIP_OK(hipMemcpyAsync(s.tpred, s.tnow, 8 * (size_t)c->nc, hipMemcpyDeviceToDevice, c->stream));
   HIP_OK(launch_predict_all(s, c->stream));
+  c->pred_full = true;
   c->sel_valid = false;  // the plan is replaced
   nbody_status r = force_all_internal(c, kF64);
   if (r != NBODY_OK) return r;
@@ -547,6 +571,7 @@ nbody_status nbody_set_state(nbody_ctx* c, const void* host_buf, size_t bytes) {
   HIP_OK(hipMemcpyAsync(c->s.tpred, c->s.tnow, 8 * (size_t)c->nc, hipMemcpyDeviceToDevice, c->stream));
   HIP_OK(launch_predict_all(c->s, c->stream));
   c->predicted = true;
+  c->pred_full = true;
   return NBODY_OK;
 }
 

@@ -40,7 +40,7 @@ hipError_t launch_reduce(const DevState& s, const int64_t* aoff, int64_t n_activ
 hipError_t launch_reduce_correct_step(const DevState& s, bool pot, hipStream_t st);
 
 // Predict every particle of every cluster to s.tpred[c] (FP64 x_p, v_p and
-// the mixed j-records).
+// every field of the mixed j-records).
 hipError_t launch_predict_all(const DevState& s, hipStream_t st);
 
 // Write the identity active list (act[i] = i, aoff = coff).
@@ -59,7 +59,8 @@ hipError_t launch_correct(const DevState& s, const int32_t* act, const int64_t* 
 // first, and again whenever t, dt or the plan changed outside the step
 // pipeline.
 hipError_t launch_select_init(const DevState& s, hipStream_t st);
-hipError_t launch_select(const DevState& s, int64_t target_items, hipStream_t st);
+// mode: force mode of the step (the predictor writes only what it reads).
+hipError_t launch_select(const DevState& s, int64_t target_items, int mode, hipStream_t st);
 
 // Mean relative error b of the FP32 hardware reciprocal square root over
 // log-uniform arguments in [1, 4); sets ctl->rsq_scale3 = 1 - 3b and

@@ -16,11 +16,18 @@ __device__ __forceinline__ void set_status(const DevState& s, int32_t bit) {
 
 // ---------------------------------------------------------------------------
 // Hermite predictor (Sect. 2.1, predictor equations) for particle i to time
-// tp; also writes the mixed j-record: hi = fl32(x_p), lo = fl32(x_p - hi),
-// FP32 velocity and mass.
-__device__ __forceinline__ void predict_one(const DevState& s, int64_t i, double tp) {
+// tp.  Writes what the force pass of `mode` and the corrector read:
+//   kF64: x_p, v_p (FP64);
+//   kMX64: x_p, the FP32 velocity of the j-record, and v_p only for members
+//          of the block (the corrector's particles);
+//   kDS: as kMX64 plus the FP32 pair hi = fl32(x_p), lo = fl32(x_p - hi);
+//   kAllRecords (predict entry point, start-up, energy): everything,
+//          including the FP32 mass of the j-record (constant otherwise).
+constexpr int kAllRecords = -1;
+__device__ __forceinline__ void predict_one(const DevState& s, int64_t i, double tp, int mode, bool member) {
   const int64_t n = s.n;
   const double h = tp - s.t[i];
+  const bool all = mode == kAllRecords;
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     const int64_t o = d * n + i;
@@ -28,18 +35,20 @@ __device__ __forceinline__ void predict_one(const DevState& s, int64_t i, double
     const double xp = x + h * (v + h * (0.5 * a + h * (k * (1.0 / 6.0))));
     const double vp = v + h * (a + h * (0.5 * k));
     s.xp[o] = xp;
-    s.vp[o] = vp;
-    const float hi = (float)xp;
-    s.jr[(JR_HX + d) * n + i] = hi;
-    s.jr[(JR_LX + d) * n + i] = (float)(xp - (double)hi);
-    s.jr[(JR_VX + d) * n + i] = (float)vp;
+    if (all || mode == kF64 || member) s.vp[o] = vp;
+    if (all || mode != kF64) s.jr[(JR_VX + d) * n + i] = (float)vp;
+    if (all || mode == kDS) {
+      const float hi = (float)xp;
+      s.jr[(JR_HX + d) * n + i] = hi;
+      s.jr[(JR_LX + d) * n + i] = (float)(xp - (double)hi);
+    }
   }
-  s.jr[JR_M * n + i] = (float)s.m[i];
+  if (all) s.jr[JR_M * n + i] = (float)s.m[i];
 }
 
 __global__ void __launch_bounds__(256) predict_all_kernel(DevState s) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < s.n; i += (int64_t)gridDim.x * blockDim.x)
-    predict_one(s, i, s.tpred[s.cid[i]]);
+    predict_one(s, i, s.tpred[s.cid[i]], kAllRecords, true);
 }
 
 hipError_t launch_predict_all(const DevState& s, hipStream_t st) {
@@ -628,7 +637,7 @@ __global__ void __launch_bounds__(kSelThreads) select_init_kernel(DevState s) {
   }
 }
 
-__global__ void __launch_bounds__(kSelThreads) select_kernel(DevState s) {
+__global__ void __launch_bounds__(kSelThreads) select_kernel(DevState s, int mode) {
   constexpr int PT = kSelChunk / kSelThreads;  // particles per thread
   __shared__ double buf[kSelThreads / 64];
   __shared__ int64_t sbuf[kSelThreads / 64];
@@ -685,7 +694,7 @@ __global__ void __launch_bounds__(kSelThreads) select_kernel(DevState s) {
   for (int u = 0; u < PT; ++u)
     if (flags & (1 << u)) s.act[pos++] = (int32_t)(i0 + u);
   if (advancing) {
-    for (int64_t i = b + tid; i < e; i += kSelThreads) predict_one(s, i, tsys);
+    for (int64_t i = b + tid; i < e; i += kSelThreads) predict_one(s, i, tsys, mode, s.t[i] + s.dt[i] == tsys);
   }
 }
 
@@ -703,8 +712,8 @@ hipError_t launch_select_init(const DevState& s, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_select(const DevState& s, int64_t target_items, hipStream_t st) {
-  hipLaunchKernelGGL(select_kernel, dim3(s.nch), dim3(kSelThreads), 0, st, s);
+hipError_t launch_select(const DevState& s, int64_t target_items, int mode, hipStream_t st) {
+  hipLaunchKernelGGL(select_kernel, dim3(s.nch), dim3(kSelThreads), 0, st, s, mode);
   if (s.nc <= 64)
     hipLaunchKernelGGL(plan_small_kernel, dim3(1), dim3(64), 0, st, s, (const int64_t*)nullptr, s.n, target_items,
                        1, (const int32_t*)s.acount);
