@@ -124,7 +124,9 @@ NBODY_API nbody_status nbody_predict(nbody_ctx *ctx, const double *t_pred);
 
 /* Pairwise acceleration, jerk and (optionally) potential (Sect. 2.1,
  * Eq. Force and the jerk by direct summation) on the listed particles from
- * every predicted particle j != i of the same cluster.
+ * every predicted particle j != i of the same cluster.  The predicted state
+ * is that of the last nbody_predict; after block steps (nbody_step), every
+ * particle is first predicted again to its cluster's current time.
  *   active_idx: device, n_active global particle ids, cluster-major and
  *               ascending inside each cluster.
  *   active_offsets: device, n_clusters+1 int64; the entries of cluster c are
@@ -137,7 +139,8 @@ NBODY_API nbody_status nbody_force(nbody_ctx *ctx, const int32_t *active_idx, co
                          int64_t n_active, double *acc, double *jerk, double *pot);
 
 /* Hermite corrector, Aarseth step and block quantisation (Sect. 2.1) for the
- * listed particles, advancing each to its cluster's last predicted time.
+ * listed particles, advancing each to its cluster's last predicted time
+ * (the prediction time of nbody_predict, or of the last block step).
  * acc, jerk: device [3][n_active], the values at the predicted time (as
  * returned by nbody_force on the same list). */
 NBODY_API nbody_status nbody_correct(nbody_ctx *ctx, const int32_t *active_idx,
