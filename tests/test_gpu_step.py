@@ -264,3 +264,45 @@ def test_diagnostics_match_oracle():
         assert np.max(np.abs(d["L"][c] - ref["L"])) <= 1e-14 * scale_l
     assert np.allclose(sim.energy(), d["E"], rtol=0, atol=0)
     sim.close()
+
+
+def test_batch_with_tiny_clusters_follows_oracle():
+    """A batch with clusters of 1, 2 and 3 particles beside larger ones
+    (one cluster per selection chunk and one spanning several): every
+    cluster, integrated in FP64 through the step graph to t = 1/4, takes
+    the oracle's block steps and ends at the oracle's state."""
+    rng = np.random.default_rng(77)
+    sizes = [1, 2, 3, 700, 1, 2500]
+    ms, xs, vs, eps = [], [], [], []
+    for n in sizes:
+        if n < 10:  # a few softened bodies
+            m = rng.random(n) + 0.5
+            m /= m.sum()
+            xc, vc = rng.standard_normal((3, n)), rng.standard_normal((3, n)) * 0.3
+            eps.append(0.05)
+        else:
+            m, xc, vc = icgen.plummer(n, 90 + n)
+            eps.append(1.0 / n)
+        ms.append(m)
+        xs.append(xc)
+        vs.append(vc)
+    m = np.concatenate(ms)
+    x = np.concatenate(xs, axis=1)
+    v = np.concatenate(vs, axis=1)
+    coff = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    banner("tiny clusters in a batch")
+    sim = _sim(m, x, v, np.array(eps), coff=coff)
+    sim.run(0.25, chunk=256)
+    assert sim.status() == 0
+    st = sim.host_state()
+    t, steps, inter = sim.progress()
+    assert np.all(t == 0.25)
+    for c, n in enumerate(sizes):
+        b, e = int(coff[c]), int(coff[c + 1])
+        ref = oracle.Sim(ms[c], xs[c], vs[c], eps[c])
+        ref.run(0.25)
+        assert steps[c] == ref.steps, (c, steps[c], ref.steps)
+        assert inter[c] == ref.interactions
+        assert np.max(np.abs(st["x"][:, b:e] - ref.x)) < 1e-9
+        assert np.max(np.abs(st["v"][:, b:e] - ref.v)) < 1e-9
+    sim.close()
