@@ -209,6 +209,12 @@ NBODY_API nbody_status nbody_get_layout(const nbody_ctx *ctx, nbody_layout *out)
  *              per i (default 1024, 1024, 48, 12: the one-lane-per-i layout
  *              is off by default); smaller blocks use 64
  *              lanes per i.  Must be non-increasing and >= 1.
+ *   small_cluster_n, small_min_block: clusters of fewer than
+ *              small_cluster_n particles use small_min_block instead of
+ *              min_block (default 16384 and 2^30, 2^30, 24, 6: small
+ *              clusters have few j-tiles, and chunks of 512 or 256 active
+ *              particles leave too few work items); small_cluster_n = 0
+ *              applies min_block to every cluster.
  *   grid: persistent workgroups of the force launch (default: 8 per CU).
  *   mixed_format: positions of the mixed kernel as double-single FP32
  *                 pairs (0) or FP64 (1, default); either way the difference
@@ -232,6 +238,8 @@ typedef struct {
     int32_t mixed_format;
     int32_t rsq_bias_correct;
     double near_tau;
+    int32_t small_cluster_n;
+    int32_t small_min_block[4];
 } nbody_tuning;
 NBODY_API nbody_status nbody_get_tuning(const nbody_ctx *ctx, nbody_tuning *out);
 NBODY_API nbody_status nbody_set_tuning(nbody_ctx *ctx, const nbody_tuning *t);

@@ -336,6 +336,11 @@ nbody_status nbody_init(nbody_ctx** out, int64_t n_total, int32_t n_clusters, co
   c->ctl.vmin[1] = 1024;
   c->ctl.vmin[2] = 48;
   c->ctl.vmin[3] = 12;
+  c->ctl.small_n = 16384;
+  c->ctl.vmin_small[0] = 1 << 30;
+  c->ctl.vmin_small[1] = 1 << 30;
+  c->ctl.vmin_small[2] = 24;
+  c->ctl.vmin_small[3] = 6;
   c->ctl.near_tau = 0.25;
 
   const size_t N = (size_t)n_total;
@@ -597,6 +602,8 @@ nbody_status nbody_get_tuning(const nbody_ctx* c, nbody_tuning* t) {
   if (!c || !t) return NBODY_E_INVAL;
   t->target_items = c->target_items;
   for (int i = 0; i < kNumVariants - 1; ++i) t->min_block[i] = c->ctl.vmin[i];
+  t->small_cluster_n = (int32_t)c->ctl.small_n;
+  for (int i = 0; i < kNumVariants - 1; ++i) t->small_min_block[i] = c->ctl.vmin_small[i];
   t->grid = c->grid;
   t->mixed_format = c->mixed_mode == kMX64 ? 1 : 0;
   t->rsq_bias_correct = c->rsq_correct;
@@ -612,9 +619,11 @@ nbody_status nbody_set_tuning(nbody_ctx* c, const nbody_tuning* t) {
   if (t->rsq_bias_correct != 0 && t->rsq_bias_correct != 1) return NBODY_E_INVAL;
   if (!(t->near_tau >= 0.0) || !isfinite(t->near_tau)) return NBODY_E_INVAL;
   for (int i = 0; i < kNumVariants - 1; ++i) {
-    if (t->min_block[i] < 1) return NBODY_E_INVAL;
+    if (t->min_block[i] < 1 || t->small_min_block[i] < 1) return NBODY_E_INVAL;
     if (i > 0 && t->min_block[i - 1] < t->min_block[i]) return NBODY_E_INVAL;
+    if (i > 0 && t->small_min_block[i - 1] < t->small_min_block[i]) return NBODY_E_INVAL;
   }
+  if (t->small_cluster_n < 0) return NBODY_E_INVAL;
   c->target_items = t->target_items;
   c->grid = t->grid;
   c->mixed_mode = t->mixed_format == 1 ? kMX64 : kDS;
@@ -622,6 +631,8 @@ nbody_status nbody_set_tuning(nbody_ctx* c, const nbody_tuning* t) {
   c->rsq_correct = t->rsq_bias_correct;
   c->ctl.near_tau = t->near_tau;
   for (int i = 0; i < kNumVariants - 1; ++i) c->ctl.vmin[i] = t->min_block[i];
+  for (int i = 0; i < kNumVariants - 1; ++i) c->ctl.vmin_small[i] = t->small_min_block[i];
+  c->ctl.small_n = t->small_cluster_n;
   destroy_graph(c);  // the captured step bakes in grid, plan target and format
   const nbody_status r = upload_ctl(c);
   if (r == NBODY_OK && recal) HIP_OK(launch_rsq_bias(c->s, c->rsq_correct, c->stream));

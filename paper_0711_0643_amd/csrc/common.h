@@ -67,6 +67,9 @@ struct Ctl {
   int64_t total_red;    // reduce work units of the current plan
   // plan tuning: smallest block size for variants 0..3 (else variant 4)
   int32_t vmin[kNumVariants - 1];
+  // the same for clusters of fewer than small_n particles
+  int32_t vmin_small[kNumVariants - 1];
+  int64_t small_n;
   // mixed kernel: pairs with m_j / R^2 > near_tau |a_i| are done in FP64
   double near_tau;
   // FP64 factors applied to the FP32 windows of the mixed kernel (bias of

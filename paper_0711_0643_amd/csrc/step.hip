@@ -113,7 +113,7 @@ __device__ __forceinline__ bool bad_range(const int64_t* aoff, const int64_t* co
 // The plan of one cluster, apart from its offsets (items, rows, units).
 __device__ __forceinline__ void plan_row(const DevState& s, const int64_t* __restrict__ aoff, int64_t n_act_bound,
                                          int64_t target_items, int count_stats, const int32_t* counts,
-                                         const int32_t* vmin, int c, Plan& P) {
+                                         const int32_t* vmin_all, int c, Plan& P) {
   const int64_t nn = s.coff[c + 1] - s.coff[c];
   int64_t na;
   if (counts) {
@@ -122,6 +122,10 @@ __device__ __forceinline__ void plan_row(const DevState& s, const int64_t* __res
     na = aoff[c + 1] - aoff[c];
     if (bad_range(aoff, s.coff, c, n_act_bound)) na = 0;
   }
+  // layout thresholds: vmin_all[0..3] for large clusters, [4..7] for those
+  // below vmin_all[8] particles
+  const int32_t* vmin = nn < (int64_t)vmin_all[kNumVariants - 1 + kNumVariants - 1] ? vmin_all + (kNumVariants - 1)
+                                                                                     : vmin_all;
   int var = kNumVariants - 1;
   for (int vv = kNumVariants - 2; vv >= 0; --vv)
     if (na >= vmin[vv]) var = vv;
@@ -173,9 +177,13 @@ __device__ void plan_body(const DevState& s, const int64_t* __restrict__ aoff, i
   const int per = (nc + 255) / 256;
   const int c0 = tid * per < nc ? tid * per : nc;
   const int c1 = c0 + per < nc ? c0 + per : nc;
-  int32_t vmin[kNumVariants - 1];
+  int32_t vmin[2 * (kNumVariants - 1) + 1];  // large-cluster, small-cluster thresholds, size cut
 #pragma unroll
-  for (int v = 0; v < kNumVariants - 1; ++v) vmin[v] = s.ctl->vmin[v];
+  for (int v = 0; v < kNumVariants - 1; ++v) {
+    vmin[v] = s.ctl->vmin[v];
+    vmin[kNumVariants - 1 + v] = s.ctl->vmin_small[v];
+  }
+  vmin[2 * (kNumVariants - 1)] = (int32_t)(s.ctl->small_n < INT32_MAX ? s.ctl->small_n : INT32_MAX);
 
   if (!counts) {
     bool bad = (tid == 0) && (aoff[0] != 0);
@@ -237,9 +245,13 @@ __device__ void plan_small(const DevState& s, const int64_t* __restrict__ aoff, 
                            int64_t target_items, int count_stats, const int32_t* counts) {
   const int c = threadIdx.x;
   const int nc = s.nc;
-  int32_t vmin[kNumVariants - 1];
+  int32_t vmin[2 * (kNumVariants - 1) + 1];  // large-cluster, small-cluster thresholds, size cut
 #pragma unroll
-  for (int v = 0; v < kNumVariants - 1; ++v) vmin[v] = s.ctl->vmin[v];
+  for (int v = 0; v < kNumVariants - 1; ++v) {
+    vmin[v] = s.ctl->vmin[v];
+    vmin[kNumVariants - 1 + v] = s.ctl->vmin_small[v];
+  }
+  vmin[2 * (kNumVariants - 1)] = (int32_t)(s.ctl->small_n < INT32_MAX ? s.ctl->small_n : INT32_MAX);
   if (!counts) {
     bool bad = (c == 0) && (aoff[0] != 0);
     if (c < nc && bad_range(aoff, s.coff, c, n_act_bound)) bad = true;

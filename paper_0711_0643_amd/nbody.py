@@ -103,6 +103,8 @@ class Tuning(ctypes.Structure):
         ("mixed_format", ctypes.c_int32),
         ("rsq_bias_correct", ctypes.c_int32),
         ("near_tau", ctypes.c_double),
+        ("small_cluster_n", ctypes.c_int32),
+        ("small_min_block", ctypes.c_int32 * 4),
     ]
 
 
@@ -296,7 +298,8 @@ class Sim:
         _check(lib().nbody_get_tuning(self._ctx, ctypes.byref(t)), "nbody_get_tuning")
         return {"target_items": t.target_items, "min_block": list(t.min_block), "grid": t.grid,
                 "mixed_format": t.mixed_format, "rsq_bias_correct": t.rsq_bias_correct,
-                "near_tau": t.near_tau}
+                "near_tau": t.near_tau, "small_cluster_n": t.small_cluster_n,
+                "small_min_block": list(t.small_min_block)}
 
     def set_tuning(self, **kw) -> None:
         cur = self.get_tuning()
@@ -309,6 +312,9 @@ class Sim:
         t.mixed_format = int(cur["mixed_format"])
         t.rsq_bias_correct = int(cur["rsq_bias_correct"])
         t.near_tau = float(cur["near_tau"])
+        t.small_cluster_n = int(cur["small_cluster_n"])
+        for i in range(4):
+            t.small_min_block[i] = int(cur["small_min_block"][i])
         _check(lib().nbody_set_tuning(self._ctx, ctypes.byref(t)), "nbody_set_tuning")
 
     def profile_force(self, enable: bool = True) -> None:

@@ -3,8 +3,9 @@
 
 What is searched (all runtime knobs of the library):
   * the i x j layout per block size -- the smallest block for the layouts
-    with 2 i per lane, 1 i per lane, 4, 16 lanes per i (min_block), chosen by
-    timing every layout at a ladder of block sizes;
+    with 2 i per lane, 1 i per lane, 4, 16 lanes per i (min_block, applied
+    to every cluster: small_cluster_n = 0), chosen by timing every layout at
+    a ladder of block sizes;
   * the j-slicing target (target_items) and the persistent grid size (grid)
     for the full block;
   * the position format of the mixed kernel (mixed_format).
@@ -139,7 +140,7 @@ def tune(sim, use_cache: bool = True, ladder=None, verbose: bool = False) -> dic
         times = {}
         for v in range(5):
             # min_block forcing layout v for every block size (non-increasing)
-            cfg = dict(base, min_block=[BIG if i < v else 1 for i in range(4)])
+            cfg = dict(base, min_block=[BIG if i < v else 1 for i in range(4)], small_cluster_n=0)
             sim.set_tuning(**cfg)
             ms, acc = _kernel_ms(sim, act, aoff)
             err = _rel(acc, ref)
@@ -157,7 +158,7 @@ def tune(sim, use_cache: bool = True, ladder=None, verbose: bool = False) -> dic
         min_block.append(min(sizes) if sizes else BIG)
     for i in range(1, 4):
         min_block[i] = min(min_block[i], min_block[i - 1])
-    tuned = dict(base, min_block=min_block)
+    tuned = dict(base, min_block=min_block, small_cluster_n=0)
 
     # full block: slicing target, grid and mixed format
     act, aoff = active(n)
@@ -203,7 +204,9 @@ def batch_candidates(cus: int):
     """Layout thresholds and slicing targets searched by tune_batch."""
     mbs = ([1024, 1024, 48, 12], [384, 192, 48, 12], [BIG, 768, 96, 12], [BIG, BIG, 48, 12], [BIG, BIG, 96, 24],
            [BIG, BIG, 24, 6], [BIG, BIG, BIG, 12])
-    return [{"min_block": list(mb), "target_items": t} for mb in mbs for t in (8 * cus, 16 * cus)]
+    # the default (size-dependent thresholds) first, then one threshold set for every cluster
+    return [{}] + [{"min_block": list(mb), "small_cluster_n": 0, "target_items": t} for mb in mbs
+                   for t in (8 * cus, 16 * cus)]
 
 
 def tune_batch(sim, replays: int = 200, t_end: float = None, use_cache: bool = True, verbose: bool = False) -> dict:

@@ -201,7 +201,7 @@ def test_layout_variants_agree():
     big = 100000
     for mb in ([1, 1, 1, 1], [big, 1, 1, 1], [big, big, 1, 1], [big, big, big, 1], [big, big, big, big]):
         banner(f"layout min_block={mb}")
-        sim.set_tuning(min_block=mb)
+        sim.set_tuning(min_block=mb, small_cluster_n=0)
         _check_fp64(_gpu_force(sim, act), ref)
     sim.close()
 
