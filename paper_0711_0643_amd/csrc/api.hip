@@ -112,7 +112,9 @@ struct nbody_ctx {
   int mixed_mode = kMX64; // position format of the mixed kernel
   int rsq_correct = 1;    // remove the mean bias of v_rsq_f32 in the mixed kernel
   hipGraph_t graph = nullptr;
-  hipGraphExec_t gexec = nullptr;
+  hipGraphExec_t gexec = nullptr;   // one block step
+  hipGraph_t graph_k = nullptr;
+  hipGraphExec_t gexec_k = nullptr; // kStepsPerGraph block steps in sequence
   int graph_mode = -1;    // force mode the graph was captured with
   int graph_pot = -1;
   bool predicted = false;
@@ -172,35 +174,52 @@ nbody_status force_all_internal(nbody_ctx* c, int mode) {
 void destroy_graph(nbody_ctx* c) {
   if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
   if (c->graph) (void)hipGraphDestroy(c->graph);
+  if (c->gexec_k) (void)hipGraphExecDestroy(c->gexec_k);
+  if (c->graph_k) (void)hipGraphDestroy(c->graph_k);
   c->gexec = nullptr;
   c->graph = nullptr;
+  c->gexec_k = nullptr;
+  c->graph_k = nullptr;
   c->graph_mode = -1;
 }
 
-// One block step = selection (with the predictor and the plan) -> force ->
-// slice reduction with the corrector.  Captured once, replayed.
-nbody_status build_graph(nbody_ctx* c) {
-  destroy_graph(c);
+// Block steps captured into graphs: one block step = selection (with the
+// predictor) -> plan -> force -> slice reduction with the corrector.  Two
+// graphs: one step, and kStepsPerGraph steps in sequence (fewer graph
+// launches and no gaps between them for long runs).  Captured once, replayed.
+constexpr int kStepsPerGraph = 32;
+
+hipError_t capture_steps(nbody_ctx* c, int steps, hipGraph_t* g) {
   const DevState& s = c->s;
   const int mode = force_mode(c);
-  if (!c->cap_stream) HIP_OK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
-  HIP_OK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed));
-  hipError_t e = launch_select(s, c->target_items, mode, c->cap_stream);
-  if (e == hipSuccess)
-    e = launch_force(s, mode, c->p.compute_pot != 0, c->ctl.near_tau > 0.0, s.act, c->grid, c->cap_stream);
-  if (e == hipSuccess) e = launch_reduce_correct_step(s, c->p.compute_pot != 0, c->cap_stream);
-  hipGraph_t g = nullptr;
-  const hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
-  if (e != hipSuccess || e2 != hipSuccess || !g) {
-    if (g) (void)hipGraphDestroy(g);
-    return NBODY_E_HIP;
+  hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed);
+  if (e != hipSuccess) return e;
+  for (int k = 0; k < steps && e == hipSuccess; ++k) {
+    e = launch_select(s, c->target_items, mode, c->cap_stream);
+    if (e == hipSuccess)
+      e = launch_force(s, mode, c->p.compute_pot != 0, c->ctl.near_tau > 0.0, s.act, c->grid, c->cap_stream);
+    if (e == hipSuccess) e = launch_reduce_correct_step(s, c->p.compute_pot != 0, c->cap_stream);
   }
-  c->graph = g;
-  if (hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0) != hipSuccess) {
+  *g = nullptr;
+  const hipError_t e2 = hipStreamEndCapture(c->cap_stream, g);
+  if (e == hipSuccess && (e2 != hipSuccess || !*g)) e = e2 != hipSuccess ? e2 : hipErrorUnknown;
+  if (e != hipSuccess && *g) {
+    (void)hipGraphDestroy(*g);
+    *g = nullptr;
+  }
+  return e;
+}
+
+nbody_status build_graph(nbody_ctx* c) {
+  destroy_graph(c);
+  if (!c->cap_stream) HIP_OK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+  if (capture_steps(c, 1, &c->graph) != hipSuccess || capture_steps(c, kStepsPerGraph, &c->graph_k) != hipSuccess ||
+      hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0) != hipSuccess ||
+      hipGraphInstantiate(&c->gexec_k, c->graph_k, nullptr, nullptr, 0) != hipSuccess) {
     destroy_graph(c);
     return NBODY_E_HIP;
   }
-  c->graph_mode = mode;
+  c->graph_mode = force_mode(c);
   c->graph_pot = c->p.compute_pot;
   return NBODY_OK;
 }
@@ -474,7 +493,9 @@ nbody_status nbody_step(nbody_ctx* c, int32_t n_block_steps, double t_end) {
     HIP_OK(launch_select_init(c->s, c->stream));
     c->sel_valid = true;
   }
-  for (int32_t i = 0; i < n_block_steps; ++i) HIP_OK(hipGraphLaunch(c->gexec, c->stream));
+  int32_t left = n_block_steps;
+  for (; left >= kStepsPerGraph; left -= kStepsPerGraph) HIP_OK(hipGraphLaunch(c->gexec_k, c->stream));
+  for (; left > 0; --left) HIP_OK(hipGraphLaunch(c->gexec, c->stream));
   c->predicted = true;
   c->pred_full = false;
   return NBODY_OK;
