@@ -9,7 +9,7 @@ namespace nb {
 enum : int { kF64 = 0, kDS = 1, kMX64 = 2 };
 
 // Selection chunk: particles per workgroup of the block-selection kernels.
-constexpr int kSelChunk = 1024;
+constexpr int kSelChunk = 256;
 constexpr int kSelThreads = 256;
 
 // Force: every work item of the current plan, persistent grid of `grid`
