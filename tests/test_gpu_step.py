@@ -306,3 +306,36 @@ def test_batch_with_tiny_clusters_follows_oracle():
         assert np.max(np.abs(st["x"][:, b:e] - ref.x)) < 1e-9
         assert np.max(np.abs(st["v"][:, b:e] - ref.v)) < 1e-9
     sim.close()
+
+
+def test_many_tiny_clusters():
+    """2000 clusters of 3 .. 30 softened bodies (more clusters than the plan
+    kernel's workgroup has threads, one selection chunk each) to t = 1/8 in
+    FP64: six clusters checked against the oracle run alone."""
+    rng = np.random.default_rng(5)
+    sizes = rng.integers(3, 31, size=2000)
+    ms, xs, vs = [], [], []
+    for n in sizes:
+        m = rng.random(n) + 0.5
+        ms.append(m / m.sum())
+        xs.append(rng.standard_normal((3, n)))
+        vs.append(rng.standard_normal((3, n)) * 0.3)
+    m = np.concatenate(ms)
+    x = np.concatenate(xs, axis=1)
+    v = np.concatenate(vs, axis=1)
+    coff = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    eps = np.full(sizes.size, 0.1)
+    banner("2000 tiny clusters")
+    sim = _sim(m, x, v, eps, coff=coff)
+    sim.run(0.125, chunk=256)
+    assert sim.status() == 0
+    st = sim.host_state()
+    t, steps, inter = sim.progress()
+    assert np.all(t == 0.125)
+    for c in (0, 1, 777, 1500, 1998, 1999):
+        b, e = int(coff[c]), int(coff[c + 1])
+        ref = oracle.Sim(ms[c], xs[c], vs[c], 0.1)
+        ref.run(0.125)
+        assert steps[c] == ref.steps and inter[c] == ref.interactions, c
+        assert np.max(np.abs(st["x"][:, b:e] - ref.x)) < 1e-11
+    sim.close()
