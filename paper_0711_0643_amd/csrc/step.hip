@@ -305,7 +305,8 @@ hipError_t launch_plan(const DevState& s, const int64_t* aoff, int64_t n_act_bou
 // of the paper's j-parallel scheme, Sect. 3).  Work unit = 256/TP entries of
 // one cluster, TP = lanes per entry (the cluster's slice count rounded up to a
 // power of two, at most 256).  Lane l adds slices l, l + TP, ... in order;
-// the TP lane sums are then combined by a fixed binary tree in LDS.  TP and
+// the lane sums of each wave are combined by a fixed binary tree of shuffles,
+// and for TP > 64 the TP / 64 wave sums by a fixed tree in LDS.  TP and
 // the order depend only on the cluster's own plan, so the bits of a cluster
 // do not depend on the rest of the batch.  Outputs: acc[d * stride + q],
 // jerk[d * stride + q], pot[q] (pot may be NULL); entries at or past the
@@ -327,8 +328,8 @@ template <bool STEP>
 __global__ void __launch_bounds__(256) reduce_kernel(DevState s, const int64_t* __restrict__ aoff,
                                                      int64_t n_bound, int n_from_aoff, double* acc, double* jerk,
                                                      double* pot, int64_t stride) {
-  __shared__ double red[7][256];
   __shared__ double wave_min[256 / 64];
+  __shared__ double wave_sum[7][256 / 64];
   const int tid = threadIdx.x;
   const int64_t n_active = n_from_aoff ? aoff[s.nc] : n_bound;
   const int64_t units = s.ctl->total_red;
@@ -354,15 +355,30 @@ __global__ void __launch_bounds__(256) reduce_kernel(DevState s, const int64_t* 
         if (pot) v[6] += s.part[6 * rows_cap + r];
       }
     }
+    // lane l of a group of wtp = min(tp, 64) lanes adds lane l + off,
+    // off = wtp/2 ... 1; a group lies inside one wave
+    const int wtp = tp < 64 ? tp : 64;
+    const int wl = tid & (wtp - 1);
+    for (int off = wtp >> 1; off > 0; off >>= 1) {
 #pragma unroll
-    for (int d = 0; d < 7; ++d) red[d][tid] = v[d];
-    __syncthreads();
-    for (int off = tp >> 1; off > 0; off >>= 1) {
-      if (lane < off) {
+      for (int d = 0; d < 7; ++d) {
+        const double o = __shfl_down(v[d], off);
+        if (wl < off) v[d] += o;
+      }
+    }
+    if (tp > 64) {  // the entry spans tp / 64 waves (tp is the same for the whole block)
+      if ((tid & 63) == 0) {
 #pragma unroll
-        for (int d = 0; d < 7; ++d) red[d][tid] += red[d][tid + off];
+        for (int d = 0; d < 7; ++d) wave_sum[d][tid >> 6] = v[d];
       }
       __syncthreads();
+      if (lane == 0) {
+        const int w = tid >> 6;
+#pragma unroll
+        for (int d = 0; d < 7; ++d)
+          v[d] = tp == 128 ? wave_sum[d][w] + wave_sum[d][w + 1]
+                           : (wave_sum[d][0] + wave_sum[d][1]) + (wave_sum[d][2] + wave_sum[d][3]);
+      }
     }
     double t_next = INFINITY;  // STEP: new t + dt of the corrected particle
     if (live && lane == 0 && q < n_active) {
@@ -371,18 +387,18 @@ __global__ void __launch_bounds__(256) reduce_kernel(DevState s, const int64_t* 
         double a1[3], k1[3];
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-          a1[d] = red[d][tid];
-          k1[d] = red[3 + d][tid];
+          a1[d] = v[d];
+          k1[d] = v[3 + d];
         }
-        if (pot) s.pot[i] = red[6][tid];
+        if (pot) s.pot[i] = v[6];
         t_next = correct_one(s, *s.ctl, c, i, e == 0, a1, k1);
       } else {
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-          acc[d * stride + q] = red[d][tid];
-          jerk[d * stride + q] = red[3 + d][tid];
+          acc[d * stride + q] = v[d];
+          jerk[d * stride + q] = v[3 + d];
         }
-        if (pot) pot[q] = red[6][tid];
+        if (pot) pot[q] = v[6];
       }
     }
     if constexpr (STEP) {
@@ -393,7 +409,7 @@ __global__ void __launch_bounds__(256) reduce_kernel(DevState s, const int64_t* 
       __syncthreads();
       if (tid == 0) s.umin[u] = fmin(fmin(wave_min[0], wave_min[1]), fmin(wave_min[2], wave_min[3]));
     }
-    __syncthreads();  // red and wave_min are reused by the next unit
+    __syncthreads();  // wave_min and wave_sum are reused by the next unit
   }
 }
 
