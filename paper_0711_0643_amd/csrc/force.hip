@@ -259,66 +259,43 @@ __device__ __forceinline__ void pair_mixed64(const typename ModeT<MODE>::I& I, c
   if (POT) A.v[6] -= mr;
 }
 
-// A window of j that may hold a near pair of particle i (cand): first the
-// exact test in FP32, m_j / R^2 > g for some pair of the window; if one is
-// found, the result is the window's FP64 sum (every pair except the dropped
-// ones: own j, padding) minus its FP32 sum B (as the caller flushed it), so
-// that adding it replaces the one by the other.  Otherwise zero.  Kept out
-// of line: it runs rarely, and inlined its FP64 temporaries would raise the
-// register count (and lower the occupancy) of the whole force kernel.
-template <int MODE, bool MASK, bool POT>
-__device__ __attribute__((noinline)) Acc64 window_f64(const typename ModeT<MODE>::Rec* tile, int jl_first, int count,
-                                                      int64_t tile_j0, int64_t j_end, int64_t i_glob,
-                                                      typename ModeT<MODE>::I I, float g, bool cand, double eps2d,
-                                                      float eps2f, Acc32 B, double ca, double cp) {
-  Acc64 R;
+// FP64 pass over the near windows of one tile, after the FP32 sweep (the
+// tile is still in LDS).  Bit p * NW + k of `flags` marks window k (F
+// entries from jl0 + k F) of i-particle p.  WIN (window test): the window's
+// FP32 sum was left out, so every pair of it except the dropped ones (own j,
+// padding) is added in FP64.  Otherwise (per-pair weights): each pair whose
+// near weight w is below 1 adds (1 - w) of its FP64 value; w is recomputed
+// with exactly the operations of the FP32 pass.  Each lane walks its own
+// windows in ascending order, so the sums do not depend on the other lanes.
+// Kept inline and rolled: at this point the FP32 window state is dead, so
+// the FP64 temporaries fit beside the totals without spilling, and no call
+// (with its register saves in scratch memory) is needed.
+template <int MODE, int F, int NW, int IPT, bool POT, bool WIN>
+__device__ __forceinline__ void near_windows_f64(const typename ModeT<MODE>::Rec* tile, int jl0, int64_t tile_j0,
+                                                 int64_t j_end, const int64_t* i_glob,
+                                                 const typename ModeT<MODE>::I* I, const float* gB, double eps2d,
+                                                 float eps2f, uint32_t flags, Acc64* A) {
 #pragma unroll
-  for (int d = 0; d < 7; ++d) R.v[d] = 0.0;
-  bool hit = false;
-  if (cand) {
-    for (int u = 0; u < count; ++u) {
-      const int64_t jg = tile_j0 + jl_first + u;
-      if (MASK && (jg == i_glob || jg >= j_end)) continue;
-      const typename ModeT<MODE>::Rec J = tile[jl_first + u];
-      const float rinv = __builtin_amdgcn_rsqf(diff32<MODE>(I, J, eps2f).r2);
-      hit |= J.m * (rinv * rinv) > g;
+  for (int p = 0; p < IPT; ++p) {
+    uint32_t f = (flags >> (p * NW)) & ((1u << NW) - 1u);
+    while (f) {
+      const int jw = jl0 + __builtin_ctz(f) * F;
+      f &= f - 1u;
+#pragma unroll 1
+      for (int u = 0; u < F; ++u) {
+        const int jl = jw + u;
+        const int64_t jg = tile_j0 + jl;
+        if (jg == i_glob[p] || jg >= j_end) continue;
+        const typename ModeT<MODE>::Rec J = tile[jl];
+        if constexpr (WIN) {
+          pair_mixed64<MODE, POT>(I[p], J, eps2d, 1.0, A[p]);
+        } else {
+          const float wt = near_weight_again(diff32<MODE>(I[p], J, eps2f), J.m, gB[p]);
+          if (wt < 1.f) pair_mixed64<MODE, POT>(I[p], J, eps2d, 1.0 - (double)wt, A[p]);
+        }
+      }
     }
   }
-  if (!hit) return R;
-  // take back the window's FP32 sum, already flushed by the caller
-#pragma unroll
-  for (int d = 0; d < 6; ++d) R.v[d] = -((double)B.v[d] * ca);
-  if (POT) R.v[6] = -((double)B.v[6] * cp);
-  for (int u = 0; u < count; ++u) {
-    const int jl = jl_first + u;
-    const int64_t jg = tile_j0 + jl;
-    if (MASK && (jg == i_glob || jg >= j_end)) continue;
-    pair_mixed64<MODE, POT>(I, tile[jl], eps2d, 1.0, R);
-  }
-  return R;
-}
-
-// FP64 re-scan of one FP32 window for one i-particle in the per-pair near
-// scheme: every pair whose near weight w is below 1 adds (1 - w) of its FP64
-// value.  Out of line for the same reason as window_f64.
-template <int MODE, bool MASK, bool POT>
-__device__ __attribute__((noinline)) Acc64 near_pairs_f64(const typename ModeT<MODE>::Rec* tile, int jl_first,
-                                                          int count, int64_t tile_j0, int64_t j_end, int64_t i_glob,
-                                                          typename ModeT<MODE>::I I, float gB, bool any, double eps2d,
-                                                          float eps2f) {
-  Acc64 R;
-#pragma unroll
-  for (int d = 0; d < 7; ++d) R.v[d] = 0.0;
-  if (!any) return R;
-  for (int u = 0; u < count; ++u) {
-    const int jl = jl_first + u;
-    const int64_t jg = tile_j0 + jl;
-    if (MASK && (jg == i_glob || jg >= j_end)) continue;
-    const typename ModeT<MODE>::Rec J = tile[jl];
-    const float wt = near_weight_again(diff32<MODE>(I, J, eps2f), J.m, gB);
-    if (wt < 1.f) pair_mixed64<MODE, POT>(I, J, eps2d, 1.0 - (double)wt, R);
-  }
-  return R;
 }
 
 // Sweep this lane's share of one LDS tile for its IPT i-particles.  jl0:
@@ -332,16 +309,16 @@ __device__ __attribute__((noinline)) Acc64 near_pairs_f64(const typename ModeT<M
 // sum, i.e. for a close neighbour with m_j / R^2 > g = tau |a_i| (|a_i| from
 // the last step).  No such pair stays in FP32; two ways to find them:
 //  * window test (layouts with one lane per i, large blocks): each lane keeps
-//    the smallest R^2 of its window (one min per pair); only when
+//    the smallest R^2 of its window (one min per pair); when
 //    m_max / R^2_min > g (m_max: largest mass of the window's 32-entry group,
-//    wmax[]) can the window hold a near pair, and then window_f64 tests its
-//    pairs exactly and, if one is near, replaces the window's FP32 sum by its
-//    FP64 sum (a near term would also spoil the rounding of the FP32 sum).
+//    wmax[]) the window may hold a near pair: its FP32 sum is left out and
+//    the whole window is summed in FP64 instead (a near term would also
+//    spoil the rounding of the FP32 sum).
 //  * per-pair weights (layouts that split j over lanes, small blocks, where
 //    clusters are often small and near pairs common): each pair gets weight
-//    0 or 1 in the FP32 window and near_pairs_f64 adds the weight-0 pairs in
-//    FP64.
-// Either re-scan is a wave-uniform branch taken only when some lane needs it.
+//    0 or 1 in the FP32 window, and the weight-0 pairs are added in FP64.
+// The FP64 work runs after the tile's FP32 sweep (near_windows_f64), in a
+// wave-uniform branch taken only when some lane marked a window.
 template <int MODE, int PER, int IPT, bool MASK, bool POT, bool NEAR>
 __device__ __forceinline__ void sweep_tile(const typename ModeT<MODE>::Rec* tile, const float* wmax, int jl0,
                                            int64_t tile_j0, int64_t j_end, const int64_t* i_glob,
@@ -363,6 +340,9 @@ __device__ __forceinline__ void sweep_tile(const typename ModeT<MODE>::Rec* tile
     constexpr bool WIN = NEAR && PER == kTile;  // window test
     constexpr bool WGT = NEAR && !WIN;          // per-pair weights
     constexpr int F = PER < 32 ? PER : 32;      // FP32 window, then flush to FP64
+    constexpr int NW = PER / F;                 // windows per tile
+    static_assert(IPT * NW <= 32, "near flags must fit 32 bits");
+    uint32_t flags = 0;  // near windows of this tile: bit p * NW + window
     for (int w = 0; w < PER; w += F) {
       Acc32 B[IPT];
       float r2min[IPT];
@@ -388,43 +368,27 @@ __device__ __forceinline__ void sweep_tile(const typename ModeT<MODE>::Rec* tile
       }
       // flush: the FP32 window times the factor that removes the mean bias
       // of the hardware reciprocal square root (ca for terms in R^-3, cp for
-      // R^-1)
+      // R^-1); a window that may hold a near pair (window test) is left out
+      // here and summed in FP64 after the sweep
 #pragma unroll
       for (int p = 0; p < IPT; ++p) {
-#pragma unroll
-        for (int d = 0; d < 6; ++d) A[p].v[d] = __builtin_fma((double)B[p].v[d], ca, A[p].v[d]);
-        if (POT) A[p].v[6] = __builtin_fma((double)B[p].v[6], cp, A[p].v[6]);
-      }
-      if constexpr (WIN) {
-        // windows that may hold a near pair: the exact test and, if it finds
-        // one, the window's FP64 sum in place of the FP32 one just added
-        bool cand[IPT], any_cand = false;
-#pragma unroll
-        for (int p = 0; p < IPT; ++p) {
-          cand[p] = wmax[(jl0 + w) >> 5] > g[p] * r2min[p];
-          any_cand |= cand[p];
+        double fa = ca, fp = cp;
+        if constexpr (WIN) {
+          const bool cand = wmax[(jl0 + w) >> 5] > g[p] * r2min[p];
+          flags |= (uint32_t)cand << (p * NW + w / F);
+          fa = cand ? 0.0 : ca;
+          fp = cand ? 0.0 : cp;
         }
-        if (__any(any_cand)) {
+        if constexpr (WGT) flags |= (uint32_t)(wmin < 1.f) << (p * NW + w / F);
 #pragma unroll
-          for (int p = 0; p < IPT; ++p) {
-            const Acc64 R = window_f64<MODE, MASK, POT>(tile, jl0 + w, F, tile_j0, j_end, i_glob[p], I[p], g[p],
-                                                        cand[p], eps2d, eps2f, B[p], ca, cp);
-#pragma unroll
-            for (int d = 0; d < 7; ++d) A[p].v[d] += R.v[d];
-          }
-        }
+        for (int d = 0; d < 6; ++d) A[p].v[d] = __builtin_fma((double)B[p].v[d], fa, A[p].v[d]);
+        if (POT) A[p].v[6] = __builtin_fma((double)B[p].v[6], fp, A[p].v[6]);
       }
-      if constexpr (WGT) {
-        if (__any(wmin < 1.f)) {  // FP64 re-scan of the pairs left out above
-#pragma unroll
-          for (int p = 0; p < IPT; ++p) {
-            const Acc64 R = near_pairs_f64<MODE, MASK, POT>(tile, jl0 + w, F, tile_j0, j_end, i_glob[p], I[p],
-                                                            gB[p], wmin < 1.f, eps2d, eps2f);
-#pragma unroll
-            for (int d = 0; d < 7; ++d) A[p].v[d] += R.v[d];
-          }
-        }
-      }
+    }
+    if constexpr (NEAR) {
+      if (__any(flags != 0u))
+        near_windows_f64<MODE, F, NW, IPT, POT, WIN>(tile, jl0, tile_j0, j_end, i_glob, I, gB, eps2d, eps2f, flags,
+                                                     A);
     }
   }
 }
@@ -454,7 +418,8 @@ __device__ void run_item(const DevState& s, const int32_t* __restrict__ act, con
   using IT = typename ModeT<MODE>::I;
   Rec* tile = reinterpret_cast<Rec*>(lds);
 
-  const int tid = threadIdx.x;
+  int tid = threadIdx.x;
+  asm volatile("" : "+v"(tid));  // opaque here: nothing derived from it is hoisted out of the item loop
   const int il = tid % SLOTS;
   const int jl = tid / SLOTS;
   const int chunk = (int)(local_item / P.slices);
