@@ -301,6 +301,28 @@ hipError_t launch_plan(const DevState& s, const int64_t* aoff, int64_t n_act_bou
   return hipGetLastError();
 }
 
+// The stored state of particle i that its corrector reads: t, dt, a, k (the
+// values from the start of its step) and the predicted x_p, v_p.
+struct CorrIn {
+  double t, dt, a0[3], k0[3], xp[3], vp[3];
+};
+
+__device__ __forceinline__ CorrIn load_corr(const DevState& s, int64_t i) {
+  CorrIn in;
+  const int64_t n = s.n;
+  in.t = s.t[i];
+  in.dt = s.dt[i];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int64_t o = d * n + i;
+    in.a0[d] = s.a[o];
+    in.k0[d] = s.k[o];
+    in.xp[d] = s.xp[o];
+    in.vp[d] = s.vp[o];
+  }
+  return in;
+}
+
 // Sum of the slice partials of every active entry (the across-processor sum
 // of the paper's j-parallel scheme, Sect. 3).  Work unit = 256/TP entries of
 // one cluster, TP = lanes per entry (the cluster's slice count rounded up to a
@@ -312,7 +334,7 @@ hipError_t launch_plan(const DevState& s, const int64_t* aoff, int64_t n_act_bou
 // jerk[d * stride + q], pot[q] (pot may be NULL); entries at or past the
 // active count are skipped.  STEP: the sums go straight to the corrector.
 __device__ __forceinline__ double correct_one(const DevState& s, const Ctl& ctl, int c, int64_t i, bool first,
-                                              const double a1[3], const double k1[3]);
+                                              const double a1[3], const double k1[3], const CorrIn& in);
 
 // Cluster of reduce unit u: the last cluster whose red_off <= u.
 __device__ __forceinline__ int cluster_of_unit(const Plan* plan, int nc, int64_t u) {
@@ -343,6 +365,15 @@ __global__ void __launch_bounds__(256) reduce_kernel(DevState s, const int64_t* 
     const int64_t e = (u - P.red_off) * epw + tid / tp;  // entry within the cluster
     const bool live = e < P.n_act;
     const int64_t q = P.act_off + e;
+    // STEP: the corrector's inputs are loaded first, so that their latency
+    // overlaps that of the slice partials
+    const bool corrects = STEP && live && lane == 0 && q < n_active;
+    int64_t i = 0;
+    CorrIn cin{};
+    if (corrects) {
+      i = s.act[q];
+      cin = load_corr(s, i);
+    }
     double v[7];
 #pragma unroll
     for (int d = 0; d < 7; ++d) v[d] = 0.0;
@@ -383,7 +414,6 @@ __global__ void __launch_bounds__(256) reduce_kernel(DevState s, const int64_t* 
     double t_next = INFINITY;  // STEP: new t + dt of the corrected particle
     if (live && lane == 0 && q < n_active) {
       if constexpr (STEP) {  // step pipeline: correct the particle right here
-        const int64_t i = s.act[q];
         double a1[3], k1[3];
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
@@ -391,7 +421,7 @@ __global__ void __launch_bounds__(256) reduce_kernel(DevState s, const int64_t* 
           k1[d] = v[3 + d];
         }
         if (pot) s.pot[i] = v[6];
-        t_next = correct_one(s, *s.ctl, c, i, e == 0, a1, k1);
+        t_next = correct_one(s, *s.ctl, c, i, e == 0, a1, k1, cin);
       } else {
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
@@ -529,28 +559,28 @@ hipError_t launch_init_steps(const DevState& s, hipStream_t st) {
 // cluster.
 // One particle: corrector, new step, state update.  i: particle, c: its
 // cluster, first: whether this entry is the cluster's first of the block
-// (it records the cluster's new time).
+// (it records the cluster's new time), in: its stored state (load_corr).
 __device__ __forceinline__ double correct_one(const DevState& s, const Ctl& ctl, int c, int64_t i, bool first,
-                                              const double a1[3], const double k1[3]) {
+                                              const double a1[3], const double k1[3], const CorrIn& in) {
   const int64_t n = s.n;
   const double t_new = s.tpred[c];
-  const double h = t_new - s.t[i];
+  const double h = t_new - in.t;
   int32_t st = 0;
   if (!(h > 0.0)) {
     set_status(s, ST_STATE);
-    return s.t[i] + s.dt[i];
+    return in.t + in.dt;
   }
   const double h2 = h * h, h3 = h2 * h, h4 = h3 * h, h5 = h4 * h;
   double a2[3], a3[3], a2p[3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     const int64_t o = d * n + i;
-    const double a0 = s.a[o], k0 = s.k[o];
+    const double a0 = in.a0[d], k0 = in.k0[d];
     const double da = a0 - a1[d];
     a2[d] = -6.0 * da / h2 - (4.0 * k0 + 2.0 * k1[d]) / h;
     a3[d] = 12.0 * da / h3 + 6.0 * (k0 + k1[d]) / h2;
-    const double xn = s.xp[o] + a2[d] * h4 / 24.0 + a3[d] * h5 / 120.0;
-    const double vn = s.vp[o] + a2[d] * h3 / 6.0 + a3[d] * h4 / 24.0;
+    const double xn = in.xp[d] + a2[d] * h4 / 24.0 + a3[d] * h5 / 120.0;
+    const double vn = in.vp[d] + a2[d] * h3 / 6.0 + a3[d] * h4 / 24.0;
     if (!isfinite(xn) || !isfinite(vn) || !isfinite(a1[d]) || !isfinite(k1[d])) st |= ST_NONFINITE;
     s.x[o] = xn;
     s.v[o] = vn;
@@ -564,7 +594,7 @@ __device__ __forceinline__ double correct_one(const DevState& s, const Ctl& ctl,
   const double na3 = norm3(a3[0], a3[1], a3[2]);
   const double den = nk * na3 + na2 * na2;
   const double raw = den == 0.0 ? INFINITY : sqrt(ctl.eta * (na * na2 + nk * nk) / den);
-  const double dt_new = quantize(raw, s.dt[i], t_new, ctl.dt_max, ctl.dt_min, &st);
+  const double dt_new = quantize(raw, in.dt, t_new, ctl.dt_max, ctl.dt_min, &st);
   s.dt[i] = dt_new;
   s.t[i] = t_new;
   if (first) s.tnow[c] = t_new;
@@ -603,7 +633,7 @@ __global__ void __launch_bounds__(256) correct_kernel(DevState s, const int32_t*
     a1[d] = acc[d * n_active + q];
     k1[d] = jerk[d * n_active + q];
   }
-  correct_one(s, ctl, c, i, q == aoff[c], a1, k1);
+  correct_one(s, ctl, c, i, q == aoff[c], a1, k1, load_corr(s, i));
 }
 
 hipError_t launch_correct(const DevState& s, const int32_t* act, const int64_t* aoff, int64_t n_active,
