@@ -24,14 +24,35 @@ __device__ __forceinline__ void set_status(const DevState& s, int32_t bit) {
 //   kAllRecords (predict entry point, start-up, energy): everything,
 //          including the FP32 mass of the j-record (constant otherwise).
 constexpr int kAllRecords = -1;
-__device__ __forceinline__ void predict_one(const DevState& s, int64_t i, double tp, int mode, bool member) {
+// Inputs of the predictor for particle i: t and x, v, a, k.
+struct PredIn {
+  double t, x[3], v[3], a[3], k[3];
+};
+
+__device__ __forceinline__ PredIn load_pred(const DevState& s, int64_t i) {
+  PredIn in;
   const int64_t n = s.n;
-  const double h = tp - s.t[i];
+  in.t = s.t[i];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int64_t o = d * n + i;
+    in.x[d] = s.x[o];
+    in.v[d] = s.v[o];
+    in.a[d] = s.a[o];
+    in.k[d] = s.k[o];
+  }
+  return in;
+}
+
+__device__ __forceinline__ void predict_from(const DevState& s, int64_t i, const PredIn& in, double tp, int mode,
+                                             bool member) {
+  const int64_t n = s.n;
+  const double h = tp - in.t;
   const bool all = mode == kAllRecords;
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     const int64_t o = d * n + i;
-    const double x = s.x[o], v = s.v[o], a = s.a[o], k = s.k[o];
+    const double x = in.x[d], v = in.v[d], a = in.a[d], k = in.k[d];
     const double xp = x + h * (v + h * (0.5 * a + h * (k * (1.0 / 6.0))));
     const double vp = v + h * (a + h * (0.5 * k));
     s.xp[o] = xp;
@@ -44,6 +65,10 @@ __device__ __forceinline__ void predict_one(const DevState& s, int64_t i, double
     }
   }
   if (all) s.jr[JR_M * n + i] = (float)s.m[i];
+}
+
+__device__ __forceinline__ void predict_one(const DevState& s, int64_t i, double tp, int mode, bool member) {
+  predict_from(s, i, load_pred(s, i), tp, mode, member);
 }
 
 __global__ void __launch_bounds__(256) predict_all_kernel(DevState s) {
@@ -696,7 +721,7 @@ __global__ void __launch_bounds__(kSelThreads) select_init_kernel(DevState s) {
 }
 
 __global__ void __launch_bounds__(kSelThreads) select_kernel(DevState s, int mode) {
-  constexpr int PT = kSelChunk / kSelThreads;  // particles per thread
+  static_assert(kSelChunk == kSelThreads, "one particle per thread");
   __shared__ double buf[kSelThreads / 64];
   __shared__ int64_t sbuf[kSelThreads / 64];
   __shared__ int64_t base_sh;
@@ -706,6 +731,21 @@ __global__ void __launch_bounds__(kSelThreads) select_kernel(DevState s, int mod
   const int64_t par = s.ctl->sel_parity;
   const double* cur = s.cm2 + (par & 1) * s.nch;
   double* nxt = s.cm2 + ((par + 1) & 1) * s.nch;
+
+  // this thread's particle: its t + dt and (for a cluster that has not
+  // reached the end time) the predictor's inputs do not depend on the block
+  // time, so they are loaded first and their latency overlaps that of the
+  // block-time reduction
+  const int64_t i = s.ch_begin[ch] + tid;
+  const bool have = i < s.ch_begin[ch + 1];
+  const bool ahead = s.tnow[c] < s.ctl->t_end;
+  double tt = INFINITY;
+  PredIn pin{};
+  if (have) {
+    if (ahead) pin = load_pred(s, i);
+    else pin.t = s.t[i];
+    tt = pin.t + s.dt[i];
+  }
 
   // block time of cluster c
   double mn = INFINITY;
@@ -718,42 +758,20 @@ __global__ void __launch_bounds__(kSelThreads) select_kernel(DevState s, int mod
   }
   const double tsys = block_min(mn, buf);
   const bool advancing = tsys <= s.ctl->t_end;
+  const bool member = have && advancing && tt == tsys;
+  if (have && advancing) predict_from(s, i, ahead ? pin : load_pred(s, i), tsys, mode, member);
 
   // members, and the smallest t + dt of the others
-  const int64_t b = s.ch_begin[ch], e = s.ch_begin[ch + 1];
-  const int64_t i0 = b + (int64_t)tid * PT;
-  int32_t flags = 0, mine = 0;
-  double rest = INFINITY;
-#pragma unroll
-  for (int u = 0; u < PT; ++u) {
-    const int64_t i = i0 + u;
-    if (i < e) {
-      const double tt = s.t[i] + s.dt[i];
-      if (advancing && tt == tsys) {
-        flags |= 1 << u;
-        ++mine;
-      } else {
-        rest = fmin(rest, tt);
-      }
-    }
-  }
-  rest = block_min(rest, buf);
-  // exclusive scan of the per-thread counts
+  const double rest = block_min(member ? INFINITY : tt, buf);
   int64_t total;
-  const int64_t before = wg_exclusive_scan(mine, sbuf, &total);
+  const int64_t before = wg_exclusive_scan(member ? 1 : 0, sbuf, &total);
   if (tid == 0) {
     nxt[ch] = rest;
     base_sh = total > 0 ? atomicAdd(&s.acount[c], (int32_t)total) : 0;
     if (advancing && ch == s.cl_ch[c]) s.tpred[c] = tsys;
   }
   __syncthreads();
-  int64_t pos = s.coff[c] + base_sh + before;
-#pragma unroll
-  for (int u = 0; u < PT; ++u)
-    if (flags & (1 << u)) s.act[pos++] = (int32_t)(i0 + u);
-  if (advancing) {
-    for (int64_t i = b + tid; i < e; i += kSelThreads) predict_one(s, i, tsys, mode, s.t[i] + s.dt[i] == tsys);
-  }
+  if (member) s.act[s.coff[c] + base_sh + before] = (int32_t)i;
 }
 
 // Plan of the step's force pass from the selection counts (one workgroup),
