@@ -161,12 +161,26 @@ nbody_status status_from_bits(int32_t bits) {
   return NBODY_OK;
 }
 
+// Whether no cluster can reach a one-lane-per-i layout: a block holds at
+// most all of its cluster, so a cluster below the threshold of layout 1 (the
+// lower of the two; thresholds do not increase with the layout index) never
+// uses layouts 0 or 1.  Then the force pass runs the kernel with only the
+// j-split layouts, which has the higher occupancy.
+bool split_only(const nbody_ctx* c) {
+  for (int k = 0; k < c->nc; ++k) {
+    const int64_t nk = c->coff[k + 1] - c->coff[k];
+    const int64_t thr = nk < c->ctl.small_n ? c->ctl.vmin_small[1] : c->ctl.vmin[1];
+    if (nk >= thr) return false;
+  }
+  return true;
+}
+
 // Force on the internal identity active list into s.fout (start-up, energy).
 nbody_status force_all_internal(nbody_ctx* c, int mode) {
   const DevState& s = c->s;
   HIP_OK(launch_identity(s, c->stream));
   HIP_OK(launch_plan(s, s.aoff, s.n, c->target_items, c->stream));
-  HIP_OK(launch_force(s, mode, true, c->ctl.near_tau > 0.0, s.act, c->grid, c->stream));
+  HIP_OK(launch_force(s, mode, true, c->ctl.near_tau > 0.0, split_only(c), s.act, c->grid, c->stream));
   HIP_OK(launch_reduce(s, s.aoff, s.n, s.fout, s.fout + 3 * s.n, s.fout + 6 * s.n, c->stream));
   return NBODY_OK;
 }
@@ -197,7 +211,8 @@ hipError_t capture_steps(nbody_ctx* c, int steps, hipGraph_t* g) {
   for (int k = 0; k < steps && e == hipSuccess; ++k) {
     e = launch_select(s, c->target_items, mode, c->cap_stream);
     if (e == hipSuccess)
-      e = launch_force(s, mode, c->p.compute_pot != 0, c->ctl.near_tau > 0.0, s.act, c->grid, c->cap_stream);
+      e = launch_force(s, mode, c->p.compute_pot != 0, c->ctl.near_tau > 0.0, split_only(c), s.act, c->grid,
+                       c->cap_stream);
     if (e == hipSuccess) e = launch_reduce_correct_step(s, c->p.compute_pot != 0, c->cap_stream);
   }
   *g = nullptr;
@@ -454,7 +469,8 @@ nbody_status nbody_force(nbody_ctx* c, const int32_t* active_idx, const int64_t*
     }
     HIP_OK(hipEventRecord(ev.first, c->stream));
   }
-  HIP_OK(launch_force(s, force_mode(c), pot != nullptr, c->ctl.near_tau > 0.0, active_idx, c->grid, c->stream));
+  HIP_OK(launch_force(s, force_mode(c), pot != nullptr, c->ctl.near_tau > 0.0, split_only(c), active_idx, c->grid,
+                      c->stream));
   if (c->profile) {
     HIP_OK(hipEventRecord(ev.second, c->stream));
     c->prof_pending.push_back(ev);

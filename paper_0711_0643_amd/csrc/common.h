@@ -16,7 +16,7 @@ enum : int32_t {
   ST_INDEX = 1,      // active index outside its cluster / bad active offsets
   ST_NONFINITE = 2,  // non-finite x, v, a or k, or NaN step criterion
   ST_DTMIN = 4,      // new step below dt_min
-  ST_STATE = 8,      // corrector asked to step by a non-positive time
+  ST_STATE = 8,      // corrector asked to step by a non-positive time, or a force work item of a layout the launched kernel lacks
 };
 
 // Threads per workgroup of every force launch; the i x j layout of a

@@ -539,10 +539,16 @@ __device__ void run_item(const DevState& s, const int32_t* __restrict__ act, con
 
 // POT: also sum the potential (partial row 6); without it row 6 is not written.
 // NEAR: FP64 evaluation of near pairs in the mixed modes.
-// Occupancy is pinned at 3 waves per SIMD (at most 168 VGPRs): left alone,
-// the near-pair variants grow past that and drop to 2 waves.
-template <int MODE, bool POT, bool NEAR>
-__global__ void __launch_bounds__(kForceThreads) __attribute__((amdgpu_waves_per_eu(3)))
+// SPLIT: only the layouts that split j over lanes (2, 3, 4).  They need at
+// most 128 VGPRs, so this kernel runs 4 waves per SIMD, against 3 (at most
+// 168 VGPRs, which the two-i-per-lane layout needs) for the kernel with
+// every layout.  The host launches it when no cluster can reach a
+// one-lane-per-i layout (its size is below that layout's threshold); a work
+// item of such a layout here is an inconsistency: it is reported and
+// skipped.  Without the pinned occupancy the near-pair variants of the full
+// kernel grow past 168 VGPRs and drop to 2 waves.
+template <int MODE, bool POT, bool NEAR, bool SPLIT>
+__global__ void __launch_bounds__(kForceThreads) __attribute__((amdgpu_waves_per_eu(SPLIT ? 4 : 3)))
 force_kernel(DevState s, const int32_t* __restrict__ act) {
   __shared__ __attribute__((aligned(16))) unsigned char lds[kLdsBytes];
   __shared__ float wmax[kTile / 32];
@@ -551,40 +557,59 @@ force_kernel(DevState s, const int32_t* __restrict__ act) {
     const int c = find_cluster(s.plan, s.nc, item);
     const Plan P = s.plan[c];
     const int64_t local = item - P.item_off;
-    switch (P.variant) {
-      case 0: run_item<MODE, 1, 2, POT, NEAR>(s, act, P, c, local, lds, wmax); break;
-      case 1: run_item<MODE, 1, 1, POT, NEAR>(s, act, P, c, local, lds, wmax); break;
-      case 2: run_item<MODE, 4, 1, POT, NEAR>(s, act, P, c, local, lds, wmax); break;
-      case 3: run_item<MODE, 16, 1, POT, NEAR>(s, act, P, c, local, lds, wmax); break;
-      default: run_item<MODE, 64, 1, POT, NEAR>(s, act, P, c, local, lds, wmax); break;
+    if constexpr (SPLIT) {
+      switch (P.variant) {
+        case 2: run_item<MODE, 4, 1, POT, NEAR>(s, act, P, c, local, lds, wmax); break;
+        case 3: run_item<MODE, 16, 1, POT, NEAR>(s, act, P, c, local, lds, wmax); break;
+        case 4: run_item<MODE, 64, 1, POT, NEAR>(s, act, P, c, local, lds, wmax); break;
+        default:
+          if (threadIdx.x == 0)
+            __hip_atomic_fetch_or(s.status, (int32_t)ST_STATE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          break;
+      }
+    } else {
+      switch (P.variant) {
+        case 0: run_item<MODE, 1, 2, POT, NEAR>(s, act, P, c, local, lds, wmax); break;
+        case 1: run_item<MODE, 1, 1, POT, NEAR>(s, act, P, c, local, lds, wmax); break;
+        case 2: run_item<MODE, 4, 1, POT, NEAR>(s, act, P, c, local, lds, wmax); break;
+        case 3: run_item<MODE, 16, 1, POT, NEAR>(s, act, P, c, local, lds, wmax); break;
+        default: run_item<MODE, 64, 1, POT, NEAR>(s, act, P, c, local, lds, wmax); break;
+      }
     }
     __syncthreads();  // LDS is reused by the next item
   }
 }
 
-template <int MODE, bool NEAR>
+template <int MODE, bool NEAR, bool SPLIT>
 static void launch_mode(const DevState& s, bool pot, const int32_t* act, int grid, hipStream_t st) {
   if (pot)
-    hipLaunchKernelGGL((force_kernel<MODE, true, NEAR>), dim3(grid), dim3(kForceThreads), 0, st, s, act);
+    hipLaunchKernelGGL((force_kernel<MODE, true, NEAR, SPLIT>), dim3(grid), dim3(kForceThreads), 0, st, s, act);
   else
-    hipLaunchKernelGGL((force_kernel<MODE, false, NEAR>), dim3(grid), dim3(kForceThreads), 0, st, s, act);
+    hipLaunchKernelGGL((force_kernel<MODE, false, NEAR, SPLIT>), dim3(grid), dim3(kForceThreads), 0, st, s, act);
 }
 
-hipError_t launch_force(const DevState& s, int mode, bool pot, bool near, const int32_t* act, int grid,
-                        hipStream_t st) {
+template <bool SPLIT>
+static hipError_t launch_family(const DevState& s, int mode, bool pot, bool near, const int32_t* act, int grid,
+                                hipStream_t st) {
   switch (mode) {
-    case kF64: launch_mode<kF64, false>(s, pot, act, grid, st); break;
+    case kF64: launch_mode<kF64, false, SPLIT>(s, pot, act, grid, st); break;
     case kDS:
-      if (near) launch_mode<kDS, true>(s, pot, act, grid, st);
-      else launch_mode<kDS, false>(s, pot, act, grid, st);
+      if (near) launch_mode<kDS, true, SPLIT>(s, pot, act, grid, st);
+      else launch_mode<kDS, false, SPLIT>(s, pot, act, grid, st);
       break;
     case kMX64:
-      if (near) launch_mode<kMX64, true>(s, pot, act, grid, st);
-      else launch_mode<kMX64, false>(s, pot, act, grid, st);
+      if (near) launch_mode<kMX64, true, SPLIT>(s, pot, act, grid, st);
+      else launch_mode<kMX64, false, SPLIT>(s, pot, act, grid, st);
       break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+hipError_t launch_force(const DevState& s, int mode, bool pot, bool near, bool split, const int32_t* act, int grid,
+                        hipStream_t st) {
+  return split ? launch_family<true>(s, mode, pot, near, act, grid, st)
+               : launch_family<false>(s, mode, pot, near, act, grid, st);
 }
 
 }  // namespace nb

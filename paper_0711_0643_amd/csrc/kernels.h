@@ -15,8 +15,10 @@ constexpr int kSelThreads = 256;
 // Force: every work item of the current plan, persistent grid of `grid`
 // workgroups.  act: the active list the plan was made for.  pot: also sum
 // the potential (partial row 6).  near: mixed modes evaluate pairs with
-// m_j / R^2 > ctl->near_tau |a_i| in FP64.
-hipError_t launch_force(const DevState& s, int mode, bool pot, bool near, const int32_t* act, int grid,
+// m_j / R^2 > ctl->near_tau |a_i| in FP64.  split: the kernel with only the
+// layouts that split j over lanes (higher occupancy); valid only when no
+// cluster can reach a one-lane-per-i layout.
+hipError_t launch_force(const DevState& s, int mode, bool pot, bool near, bool split, const int32_t* act, int grid,
                         hipStream_t st);
 
 // Plan the force pass for the active offsets `aoff` (device, nc+1) of an

@@ -206,6 +206,25 @@ def test_layout_variants_agree():
     sim.close()
 
 
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
+def test_split_layout_kernel_matches_full_kernel_bitwise(precision):
+    """When no cluster can reach a one-lane-per-i layout the library runs a
+    kernel holding only the j-split layouts (higher occupancy).  For the same
+    layout it must give the same bits as the kernel with every layout."""
+    n = 2000
+    m, x, v = icgen.plummer(n, 23)
+    act = icgen.active_subset(n, 300)
+    sim = _sim(m, x, v, 1 / n, precision)
+    out = []
+    for mb in ([100000, 100000, 1, 1], [n, n, 1, 1]):  # block of 300 -> 4 lanes per i in both
+        banner(f"precision {precision} min_block={mb}")
+        sim.set_tuning(min_block=mb, small_cluster_n=0)
+        acc, jerk, _ = _gpu_force(sim, act, pot=False)
+        out.append((acc, jerk))
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+    sim.close()
+
+
 def test_empty_block_is_a_no_op():
     import paper_0711_0643_amd as nb
 
