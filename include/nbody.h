@@ -214,7 +214,11 @@ NBODY_API nbody_status nbody_get_layout(const nbody_ctx *ctx, nbody_layout *out)
  *              min_block (default 16384 and 2^30, 2^30, 24, 6: small
  *              clusters have few j-tiles, and chunks of 512 or 256 active
  *              particles leave too few work items); small_cluster_n = 0
- *              applies min_block to every cluster.
+ *              applies min_block to every cluster.  When no cluster is as
+ *              large as its threshold for one lane per i (the second
+ *              entry), the force pass runs a kernel build with only the
+ *              j-split layouts, at higher occupancy; results per layout
+ *              are the same bits either way.
  *   grid: persistent workgroups of the force launch (default: 8 per CU).
  *   mixed_format: positions of the mixed kernel as double-single FP32
  *                 pairs (0) or FP64 (1, default); either way the difference
