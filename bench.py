@@ -460,7 +460,7 @@ def main():
             "unit": "TFLOP/s",
             "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
             "traffic": recorded_traffic(),
-            "kernel": "nb::force_kernel<2, false, true> (mixed, FP64 positions, near pairs in FP64)",
+            "kernel": "nb::force_kernel<2, false, true, false> (mixed, FP64 positions, near pairs in FP64, all layouts)",
             "flops_per_interaction": FLOPS_PER_INTERACTION,
             "interactions_per_launch": inter_step,
             "kernel_ms": round(mx["kernel_s"] * 1e3, 4),
