@@ -206,6 +206,25 @@ def test_layout_variants_agree():
     sim.close()
 
 
+def test_double_single_format_matches_oracle():
+    """The mixed kernel with double-single positions (mixed_format = 0:
+    dr = (hi_j - hi_i) + (lo_j - lo_i) in FP32) passes the mixed gate in
+    every layout, in both kernel builds."""
+    n = 3000
+    m, x, v = icgen.plummer(n, 24)
+    eps = 1.0 / n
+    act = icgen.active_subset(n, 700, seed=9)
+    ref = oracle.force(m, x, v, eps, act)
+    absum = oracle.force_abs(m, x, v, eps, act)
+    sim = _sim(m, x, v, eps, 1)
+    big = 100000
+    for mb in ([1, 1, 1, 1], [big, 1, 1, 1], [big, big, 1, 1], [big, big, big, 1], [big, big, big, big]):
+        banner(f"double-single min_block={mb}")
+        sim.set_tuning(min_block=mb, small_cluster_n=0, mixed_format=0)
+        _check_mixed(_gpu_force(sim, act), ref, absum)
+    sim.close()
+
+
 @pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
 def test_split_layout_kernel_matches_full_kernel_bitwise(precision):
     """When no cluster can reach a one-lane-per-i layout the library runs a
