@@ -2,8 +2,9 @@
 //
 // The library owns no device memory: nbody_init carves the caller's
 // workspace into the arrays of DevState, and every call enqueues kernels on
-// the context's stream.  nbody_step captures one block step (select ->
-// plan -> force -> correct) into a HIP graph once and replays it.
+// the context's stream.  nbody_step captures block steps (select -> plan
+// -> force -> correct; no plan kernel with a single cluster) into HIP
+// graphs once and replays them.
 #include <math.h>
 #include <stddef.h>
 #include <stdio.h>
@@ -69,7 +70,7 @@ Layout make_layout(int64_t n, int32_t nc) {
   L.inter = take(8 * C);
   L.steps = take(8 * C);
   L.cm2 = take(16 * (size_t)L.nch_max);
-  L.acount = take(4 * C);
+  L.acount = take(8 * C);  // two halves of int32 counters, by step parity
   L.umin = take(8 * N);
   L.act = take(4 * N);
   L.aoff = take(8 * (C + 1));
@@ -111,10 +112,11 @@ struct nbody_ctx {
   int target_items = 2048;  // work items a force pass aims at per cluster
   int mixed_mode = kMX64; // position format of the mixed kernel
   int rsq_correct = 1;    // remove the mean bias of v_rsq_f32 in the mixed kernel
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t gexec = nullptr;   // one block step
+  hipGraph_t graph[2] = {nullptr, nullptr};
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};  // one block step, of parity 0 and 1
   hipGraph_t graph_k = nullptr;
-  hipGraphExec_t gexec_k = nullptr; // kStepsPerGraph block steps in sequence
+  hipGraphExec_t gexec_k = nullptr;  // kStepsPerGraph block steps in sequence, from parity 0
+  int parity = 0;  // parity of the next block step (which halves of the selection buffers it uses)
   int graph_mode = -1;    // force mode the graph was captured with
   int graph_pot = -1;
   bool predicted = false;
@@ -180,40 +182,47 @@ nbody_status force_all_internal(nbody_ctx* c, int mode) {
   const DevState& s = c->s;
   HIP_OK(launch_identity(s, c->stream));
   HIP_OK(launch_plan(s, s.aoff, s.n, c->target_items, c->stream));
-  HIP_OK(launch_force(s, mode, true, c->ctl.near_tau > 0.0, split_only(c), s.act, c->grid, c->stream));
+  HIP_OK(launch_force(s, mode, true, c->ctl.near_tau > 0.0, split_only(c), s.act, c->grid, -1, c->target_items,
+                      c->stream));
   HIP_OK(launch_reduce(s, s.aoff, s.n, s.fout, s.fout + 3 * s.n, s.fout + 6 * s.n, c->stream));
   return NBODY_OK;
 }
 
 void destroy_graph(nbody_ctx* c) {
-  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
-  if (c->graph) (void)hipGraphDestroy(c->graph);
+  for (int p = 0; p < 2; ++p) {
+    if (c->gexec[p]) (void)hipGraphExecDestroy(c->gexec[p]);
+    if (c->graph[p]) (void)hipGraphDestroy(c->graph[p]);
+    c->gexec[p] = nullptr;
+    c->graph[p] = nullptr;
+  }
   if (c->gexec_k) (void)hipGraphExecDestroy(c->gexec_k);
   if (c->graph_k) (void)hipGraphDestroy(c->graph_k);
-  c->gexec = nullptr;
-  c->graph = nullptr;
   c->gexec_k = nullptr;
   c->graph_k = nullptr;
   c->graph_mode = -1;
 }
 
 // Block steps captured into graphs: one block step = selection (with the
-// predictor) -> plan -> force -> slice reduction with the corrector.  Two
-// graphs: one step, and kStepsPerGraph steps in sequence (fewer graph
-// launches and no gaps between them for long runs).  Captured once, replayed.
+// predictor) -> plan (several clusters only) -> force -> slice reduction
+// with the corrector.  Each step carries its parity (which halves of the
+// selection buffers it uses) as a launch argument, alternating 0, 1, 0, ...
+// Three graphs: one step of parity 0, one of parity 1, and kStepsPerGraph
+// steps from parity 0 (fewer graph launches and no gaps between them for
+// long runs).  Captured once, replayed; the host tracks the parity.
 constexpr int kStepsPerGraph = 32;
 
-hipError_t capture_steps(nbody_ctx* c, int steps, hipGraph_t* g) {
+hipError_t capture_steps(nbody_ctx* c, int steps, int par0, hipGraph_t* g) {
   const DevState& s = c->s;
   const int mode = force_mode(c);
   hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed);
   if (e != hipSuccess) return e;
   for (int k = 0; k < steps && e == hipSuccess; ++k) {
-    e = launch_select(s, c->target_items, mode, c->cap_stream);
+    const int par = (par0 + k) & 1;
+    e = launch_select(s, c->target_items, mode, par, c->cap_stream);
     if (e == hipSuccess)
-      e = launch_force(s, mode, c->p.compute_pot != 0, c->ctl.near_tau > 0.0, split_only(c), s.act, c->grid,
-                       c->cap_stream);
-    if (e == hipSuccess) e = launch_reduce_correct_step(s, c->p.compute_pot != 0, c->cap_stream);
+      e = launch_force(s, mode, c->p.compute_pot != 0, c->ctl.near_tau > 0.0, split_only(c), s.act, c->grid, par,
+                       c->target_items, c->cap_stream);
+    if (e == hipSuccess) e = launch_reduce_correct_step(s, c->p.compute_pot != 0, par, c->target_items, c->cap_stream);
   }
   *g = nullptr;
   const hipError_t e2 = hipStreamEndCapture(c->cap_stream, g);
@@ -228,8 +237,11 @@ hipError_t capture_steps(nbody_ctx* c, int steps, hipGraph_t* g) {
 nbody_status build_graph(nbody_ctx* c) {
   destroy_graph(c);
   if (!c->cap_stream) HIP_OK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
-  if (capture_steps(c, 1, &c->graph) != hipSuccess || capture_steps(c, kStepsPerGraph, &c->graph_k) != hipSuccess ||
-      hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0) != hipSuccess ||
+  static_assert(kStepsPerGraph % 2 == 0, "a run of steps must return to parity 0");
+  if (capture_steps(c, 1, 0, &c->graph[0]) != hipSuccess || capture_steps(c, 1, 1, &c->graph[1]) != hipSuccess ||
+      capture_steps(c, kStepsPerGraph, 0, &c->graph_k) != hipSuccess ||
+      hipGraphInstantiate(&c->gexec[0], c->graph[0], nullptr, nullptr, 0) != hipSuccess ||
+      hipGraphInstantiate(&c->gexec[1], c->graph[1], nullptr, nullptr, 0) != hipSuccess ||
       hipGraphInstantiate(&c->gexec_k, c->graph_k, nullptr, nullptr, 0) != hipSuccess) {
     destroy_graph(c);
     return NBODY_E_HIP;
@@ -470,7 +482,7 @@ nbody_status nbody_force(nbody_ctx* c, const int32_t* active_idx, const int64_t*
     HIP_OK(hipEventRecord(ev.first, c->stream));
   }
   HIP_OK(launch_force(s, force_mode(c), pot != nullptr, c->ctl.near_tau > 0.0, split_only(c), active_idx, c->grid,
-                      c->stream));
+                      -1, c->target_items, c->stream));
   if (c->profile) {
     HIP_OK(hipEventRecord(ev.second, c->stream));
     c->prof_pending.push_back(ev);
@@ -496,7 +508,7 @@ nbody_status nbody_step(nbody_ctx* c, int32_t n_block_steps, double t_end) {
   if (!c || n_block_steps < 0 || !(t_end >= 0.0) || !isfinite(t_end)) return NBODY_E_INVAL;
   if (fmod(t_end, c->p.dt_max) != 0.0) return NBODY_E_INVAL;
   if (n_block_steps == 0) return NBODY_OK;
-  if (!c->gexec || c->graph_mode != force_mode(c) || c->graph_pot != c->p.compute_pot) {
+  if (!c->gexec_k || c->graph_mode != force_mode(c) || c->graph_pot != c->p.compute_pot) {
     const nbody_status r = build_graph(c);
     if (r != NBODY_OK) return r;
   }
@@ -506,12 +518,20 @@ nbody_status nbody_step(nbody_ctx* c, int32_t n_block_steps, double t_end) {
     HIP_OK(hipStreamSynchronize(c->stream));
   }
   if (!c->sel_valid) {
-    HIP_OK(launch_select_init(c->s, c->stream));
+    HIP_OK(launch_select_init(c->s, c->parity, c->stream));
     c->sel_valid = true;
   }
-  int32_t left = n_block_steps;
-  for (; left >= kStepsPerGraph; left -= kStepsPerGraph) HIP_OK(hipGraphLaunch(c->gexec_k, c->stream));
-  for (; left > 0; --left) HIP_OK(hipGraphLaunch(c->gexec, c->stream));
+  // runs of kStepsPerGraph steps start (and end) at parity 0
+  for (int32_t left = n_block_steps; left > 0;) {
+    if (c->parity == 0 && left >= kStepsPerGraph) {
+      HIP_OK(hipGraphLaunch(c->gexec_k, c->stream));
+      left -= kStepsPerGraph;
+    } else {
+      HIP_OK(hipGraphLaunch(c->gexec[c->parity], c->stream));
+      c->parity ^= 1;
+      left -= 1;
+    }
+  }
   c->predicted = true;
   c->pred_full = false;
   return NBODY_OK;

@@ -78,9 +78,6 @@ struct Ctl {
   double rsq_scale1;
   double rsq_bias;  // measured mean relative error of v_rsq_f32
   int32_t pad3[2];
-  // step pipeline (device-owned): which half of cm2 holds the current chunk
-  // minima
-  int64_t sel_parity;
 };
 
 struct DevState {
@@ -109,7 +106,7 @@ struct DevState {
   double* inter;   // [nc] pairwise interactions evaluated
   int64_t* steps;  // [nc] block steps taken
   double* cm2;     // [2][nch] per chunk: smallest t + dt of the particles the last selection left out
-  int32_t* acount; // [nc] block size of each cluster (selection counter)
+  int32_t* acount; // [2][nc] block size of each cluster (selection counters, one half per step parity)
   double* umin;    // [n] per reduce unit: smallest new t + dt of the particles it corrected
   int32_t* act;    // [n] active list (step pipeline: cluster c's block at act[coff[c]...])
   int64_t* aoff;   // [nc+1] active offsets of the internal all-particle passes
@@ -120,5 +117,66 @@ struct DevState {
   double* fout;    // [7][n] reduced force of internal passes (a, k, pot)
   int32_t* status;
 };
+
+// Layout and slicing of a cluster of nn particles whose block has na
+// members, from the layout thresholds vmin_all (min_block[0..3],
+// small_min_block[0..3], small_cluster_n) and the slicing target: as many
+// j-slices as bring the cluster alone to about target_items work items, at
+// most one per LDS tile and at most what the cluster's partial-row budget
+// allows.  Offsets (item_off, slot_base, act_off, red_off) are not set.
+__device__ inline void plan_layout(int64_t na, int64_t nn, int64_t target_items, const int32_t* vmin_all, Plan& P) {
+  const int32_t* vmin = nn < (int64_t)vmin_all[2 * (kNumVariants - 1)] ? vmin_all + (kNumVariants - 1) : vmin_all;
+  int var = kNumVariants - 1;
+  for (int vv = kNumVariants - 2; vv >= 0; --vv)
+    if (na >= vmin[vv]) var = vv;
+  const int64_t iwg = variant_iwg(var);
+  const int64_t chunks = (na + iwg - 1) / iwg;
+  int64_t S = 1;
+  if (chunks > 0) {
+    const int64_t smax_tiles = (nn + kTile - 1) / kTile;
+    const int64_t smax_rows = (kRowsPerParticle * nn + kRowsPerCluster) / na;
+    S = (target_items + chunks - 1) / chunks;
+    if (S > smax_tiles) S = smax_tiles;
+    if (S > smax_rows) S = smax_rows;
+    if (S < 1) S = 1;
+  }
+  int64_t slen = (nn + S - 1) / S;
+  slen = (slen + kTile - 1) / kTile * kTile;
+  S = (nn + slen - 1) / slen;
+  P.n_act = (int32_t)na;
+  P.variant = var;
+  P.chunks = (int32_t)chunks;
+  P.slices = (int32_t)S;
+  P.slice_len = (int32_t)slen;
+  int tp = 1;  // reduce lanes per entry
+  while (tp < S && tp < 256) tp <<= 1;
+  P.red_tp = tp;
+}
+
+__device__ inline void load_thresholds(const Ctl* ctl, int32_t* vmin_all) {
+#pragma unroll
+  for (int v = 0; v < kNumVariants - 1; ++v) {
+    vmin_all[v] = ctl->vmin[v];
+    vmin_all[kNumVariants - 1 + v] = ctl->vmin_small[v];
+  }
+  vmin_all[2 * (kNumVariants - 1)] = (int32_t)(ctl->small_n < INT32_MAX ? ctl->small_n : INT32_MAX);
+}
+
+// Reduce work units of a cluster's plan.
+__device__ inline int64_t plan_units(const Plan& P) {
+  return (P.n_act + (256 / P.red_tp) - 1) / (256 / P.red_tp);
+}
+
+// The plan of the step pipeline when there is a single cluster: its block
+// size is the selection counter of this step's parity, its offsets are 0.
+// The selection, force and reduction kernels each compute it for
+// themselves, so a step needs no plan kernel.
+__device__ inline Plan plan_single(const DevState& s, int par, int64_t target_items) {
+  int32_t vmin_all[2 * (kNumVariants - 1) + 1];
+  load_thresholds(s.ctl, vmin_all);
+  Plan P{};
+  plan_layout(s.acount[par], s.n, target_items, vmin_all, P);
+  return P;
+}
 
 }  // namespace nb

@@ -547,15 +547,26 @@ __device__ void run_item(const DevState& s, const int32_t* __restrict__ act, con
 // item of such a layout here is an inconsistency: it is reported and
 // skipped.  Without the pinned occupancy the near-pair variants of the full
 // kernel grow past 168 VGPRs and drop to 2 waves.
+// par >= 0 with a single cluster (the step pipeline): the plan follows from
+// that step parity's selection count (plan_single); otherwise it is read
+// from s.plan.
 template <int MODE, bool POT, bool NEAR, bool SPLIT>
 __global__ void __launch_bounds__(kForceThreads) __attribute__((amdgpu_waves_per_eu(SPLIT ? 4 : 3)))
-force_kernel(DevState s, const int32_t* __restrict__ act) {
+force_kernel(DevState s, const int32_t* __restrict__ act, int par, int64_t target_items) {
   __shared__ __attribute__((aligned(16))) unsigned char lds[kLdsBytes];
   __shared__ float wmax[kTile / 32];
-  const int64_t total = s.ctl->total_items;
+  const bool single = par >= 0 && s.nc == 1;
+  Plan P1{};
+  int64_t total;
+  if (single) {
+    P1 = plan_single(s, par, target_items);
+    total = (int64_t)P1.chunks * P1.slices;
+  } else {
+    total = s.ctl->total_items;
+  }
   for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
-    const int c = find_cluster(s.plan, s.nc, item);
-    const Plan P = s.plan[c];
+    const int c = single ? 0 : find_cluster(s.plan, s.nc, item);
+    const Plan P = single ? P1 : s.plan[c];
     const int64_t local = item - P.item_off;
     if constexpr (SPLIT) {
       switch (P.variant) {
@@ -580,26 +591,35 @@ force_kernel(DevState s, const int32_t* __restrict__ act) {
   }
 }
 
+struct ForceLaunch {
+  const DevState& s;
+  const int32_t* act;
+  int grid, par;
+  int64_t target_items;
+  hipStream_t st;
+};
+
 template <int MODE, bool NEAR, bool SPLIT>
-static void launch_mode(const DevState& s, bool pot, const int32_t* act, int grid, hipStream_t st) {
+static void launch_mode(const ForceLaunch& L, bool pot) {
   if (pot)
-    hipLaunchKernelGGL((force_kernel<MODE, true, NEAR, SPLIT>), dim3(grid), dim3(kForceThreads), 0, st, s, act);
+    hipLaunchKernelGGL((force_kernel<MODE, true, NEAR, SPLIT>), dim3(L.grid), dim3(kForceThreads), 0, L.st, L.s,
+                       L.act, L.par, L.target_items);
   else
-    hipLaunchKernelGGL((force_kernel<MODE, false, NEAR, SPLIT>), dim3(grid), dim3(kForceThreads), 0, st, s, act);
+    hipLaunchKernelGGL((force_kernel<MODE, false, NEAR, SPLIT>), dim3(L.grid), dim3(kForceThreads), 0, L.st, L.s,
+                       L.act, L.par, L.target_items);
 }
 
 template <bool SPLIT>
-static hipError_t launch_family(const DevState& s, int mode, bool pot, bool near, const int32_t* act, int grid,
-                                hipStream_t st) {
+static hipError_t launch_family(const ForceLaunch& L, int mode, bool pot, bool near) {
   switch (mode) {
-    case kF64: launch_mode<kF64, false, SPLIT>(s, pot, act, grid, st); break;
+    case kF64: launch_mode<kF64, false, SPLIT>(L, pot); break;
     case kDS:
-      if (near) launch_mode<kDS, true, SPLIT>(s, pot, act, grid, st);
-      else launch_mode<kDS, false, SPLIT>(s, pot, act, grid, st);
+      if (near) launch_mode<kDS, true, SPLIT>(L, pot);
+      else launch_mode<kDS, false, SPLIT>(L, pot);
       break;
     case kMX64:
-      if (near) launch_mode<kMX64, true, SPLIT>(s, pot, act, grid, st);
-      else launch_mode<kMX64, false, SPLIT>(s, pot, act, grid, st);
+      if (near) launch_mode<kMX64, true, SPLIT>(L, pot);
+      else launch_mode<kMX64, false, SPLIT>(L, pot);
       break;
     default: return hipErrorInvalidValue;
   }
@@ -607,9 +627,9 @@ static hipError_t launch_family(const DevState& s, int mode, bool pot, bool near
 }
 
 hipError_t launch_force(const DevState& s, int mode, bool pot, bool near, bool split, const int32_t* act, int grid,
-                        hipStream_t st) {
-  return split ? launch_family<true>(s, mode, pot, near, act, grid, st)
-               : launch_family<false>(s, mode, pot, near, act, grid, st);
+                        int par, int64_t target_items, hipStream_t st) {
+  const ForceLaunch L{s, act, grid, par, target_items, st};
+  return split ? launch_family<true>(L, mode, pot, near) : launch_family<false>(L, mode, pot, near);
 }
 
 }  // namespace nb

@@ -17,9 +17,11 @@ constexpr int kSelThreads = 256;
 // the potential (partial row 6).  near: mixed modes evaluate pairs with
 // m_j / R^2 > ctl->near_tau |a_i| in FP64.  split: the kernel with only the
 // layouts that split j over lanes (higher occupancy); valid only when no
-// cluster can reach a one-lane-per-i layout.
+// cluster can reach a one-lane-per-i layout.  par: step parity in the step
+// pipeline (with a single cluster the plan then comes from that parity's
+// selection count and target_items), -1 for the plan in s.plan.
 hipError_t launch_force(const DevState& s, int mode, bool pot, bool near, bool split, const int32_t* act, int grid,
-                        hipStream_t st);
+                        int par, int64_t target_items, hipStream_t st);
 
 // Plan the force pass for the active offsets `aoff` (device, nc+1) of an
 // active list of at most n_act_bound entries.  target_items: work items aimed
@@ -38,8 +40,10 @@ hipError_t launch_reduce(const DevState& s, const int64_t* aoff, int64_t n_activ
 
 // Step pipeline: the same for the active list built by the selection, each
 // sum handed straight to the corrector (pot: keep phi); records the smallest
-// new t + dt per reduce unit for the next selection.
-hipError_t launch_reduce_correct_step(const DevState& s, bool pot, hipStream_t st);
+// new t + dt per reduce unit for the next selection and clears the
+// selection counters of the other parity.  par, target_items: as for
+// launch_force.
+hipError_t launch_reduce_correct_step(const DevState& s, bool pot, int par, int64_t target_items, hipStream_t st);
 
 // Predict every particle of every cluster to s.tpred[c] (FP64 x_p, v_p and
 // every field of the mixed j-records).
@@ -56,13 +60,14 @@ hipError_t launch_correct(const DevState& s, const int32_t* act, const int64_t* 
                           const double* acc, const double* jerk, hipStream_t st);
 
 
-// Step pipeline: block selection with the predictor (one kernel), then the
-// plan of the force pass (count_stats on).  launch_select_init must run
-// first, and again whenever t, dt or the plan changed outside the step
-// pipeline.
-hipError_t launch_select_init(const DevState& s, hipStream_t st);
+// Step pipeline: block selection with the predictor (one kernel), then,
+// with several clusters, the plan of the force pass (count_stats on).  par:
+// the step's parity (0 or 1), alternating from step to step.
+// launch_select_init (with the parity of the next step) must run first, and
+// again whenever t, dt or the plan changed outside the step pipeline.
+hipError_t launch_select_init(const DevState& s, int par, hipStream_t st);
 // mode: force mode of the step (the predictor writes only what it reads).
-hipError_t launch_select(const DevState& s, int64_t target_items, int mode, hipStream_t st);
+hipError_t launch_select(const DevState& s, int64_t target_items, int mode, int par, hipStream_t st);
 
 // Mean relative error b of the FP32 hardware reciprocal square root over
 // log-uniform arguments in [1, 4); sets ctl->rsq_scale3 = 1 - 3b and

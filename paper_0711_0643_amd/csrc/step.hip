@@ -147,35 +147,7 @@ __device__ __forceinline__ void plan_row(const DevState& s, const int64_t* __res
     na = aoff[c + 1] - aoff[c];
     if (bad_range(aoff, s.coff, c, n_act_bound)) na = 0;
   }
-  // layout thresholds: vmin_all[0..3] for large clusters, [4..7] for those
-  // below vmin_all[8] particles
-  const int32_t* vmin = nn < (int64_t)vmin_all[kNumVariants - 1 + kNumVariants - 1] ? vmin_all + (kNumVariants - 1)
-                                                                                     : vmin_all;
-  int var = kNumVariants - 1;
-  for (int vv = kNumVariants - 2; vv >= 0; --vv)
-    if (na >= vmin[vv]) var = vv;
-  const int64_t iwg = variant_iwg(var);
-  const int64_t chunks = (na + iwg - 1) / iwg;
-  int64_t S = 1;
-  if (chunks > 0) {
-    const int64_t smax_tiles = (nn + kTile - 1) / kTile;
-    const int64_t smax_rows = (kRowsPerParticle * nn + kRowsPerCluster) / na;
-    S = (target_items + chunks - 1) / chunks;
-    if (S > smax_tiles) S = smax_tiles;
-    if (S > smax_rows) S = smax_rows;
-    if (S < 1) S = 1;
-  }
-  int64_t slen = (nn + S - 1) / S;
-  slen = (slen + kTile - 1) / kTile * kTile;
-  S = (nn + slen - 1) / slen;
-  P.n_act = (int32_t)na;
-  P.variant = var;
-  P.chunks = (int32_t)chunks;
-  P.slices = (int32_t)S;
-  P.slice_len = (int32_t)slen;
-  int tp = 1;
-  while (tp < S && tp < 256) tp <<= 1;
-  P.red_tp = tp;
+  plan_layout(na, nn, target_items, vmin_all, P);
   if (count_stats && na > 0) {  // block-step counters (one writer per cluster)
     s.inter[c] += (double)na * (double)nn;
     s.steps[c] += 1;
@@ -187,9 +159,6 @@ __device__ __forceinline__ void plan_row(const DevState& s, const int64_t* __res
   }
 }
 
-__device__ __forceinline__ int64_t plan_units(const Plan& P) {
-  return (P.n_act + (256 / P.red_tp) - 1) / (256 / P.red_tp);
-}
 
 // The plan, computed by one workgroup of 256 threads.
 // counts != NULL (step pipeline): cluster c's block is counts[c] entries of
@@ -203,12 +172,7 @@ __device__ void plan_body(const DevState& s, const int64_t* __restrict__ aoff, i
   const int c0 = tid * per < nc ? tid * per : nc;
   const int c1 = c0 + per < nc ? c0 + per : nc;
   int32_t vmin[2 * (kNumVariants - 1) + 1];  // large-cluster, small-cluster thresholds, size cut
-#pragma unroll
-  for (int v = 0; v < kNumVariants - 1; ++v) {
-    vmin[v] = s.ctl->vmin[v];
-    vmin[kNumVariants - 1 + v] = s.ctl->vmin_small[v];
-  }
-  vmin[2 * (kNumVariants - 1)] = (int32_t)(s.ctl->small_n < INT32_MAX ? s.ctl->small_n : INT32_MAX);
+  load_thresholds(s.ctl, vmin);
 
   if (!counts) {
     bool bad = (tid == 0) && (aoff[0] != 0);
@@ -271,12 +235,7 @@ __device__ void plan_small(const DevState& s, const int64_t* __restrict__ aoff, 
   const int c = threadIdx.x;
   const int nc = s.nc;
   int32_t vmin[2 * (kNumVariants - 1) + 1];  // large-cluster, small-cluster thresholds, size cut
-#pragma unroll
-  for (int v = 0; v < kNumVariants - 1; ++v) {
-    vmin[v] = s.ctl->vmin[v];
-    vmin[kNumVariants - 1 + v] = s.ctl->vmin_small[v];
-  }
-  vmin[2 * (kNumVariants - 1)] = (int32_t)(s.ctl->small_n < INT32_MAX ? s.ctl->small_n : INT32_MAX);
+  load_thresholds(s.ctl, vmin);
   if (!counts) {
     bool bad = (c == 0) && (aoff[0] != 0);
     if (c < nc && bad_range(aoff, s.coff, c, n_act_bound)) bad = true;
@@ -303,12 +262,11 @@ __device__ void plan_small(const DevState& s, const int64_t* __restrict__ aoff, 
 
 __global__ void __launch_bounds__(64) plan_small_kernel(DevState s, const int64_t* __restrict__ aoff,
                                                         int64_t n_act_bound, int64_t target_items, int count_stats,
-                                                        const int32_t* counts) {
+                                                        int32_t* counts) {
   plan_small(s, aoff, n_act_bound, target_items, count_stats, counts);
-  if (counts) {  // step pipeline: hand the counters and the cm2 half on to the next step
-    if ((int)threadIdx.x < s.nc) s.acount[threadIdx.x] = 0;
-    if (threadIdx.x == 0) s.ctl->sel_parity += 1;
-  }
+  // step pipeline: this half of the counters is read; clear it for the step
+  // after next, which counts into it again
+  if (counts && (int)threadIdx.x < s.nc) counts[threadIdx.x] = 0;
 }
 
 __global__ void __launch_bounds__(256) plan_kernel(DevState s, const int64_t* __restrict__ aoff,
@@ -320,7 +278,7 @@ hipError_t launch_plan(const DevState& s, const int64_t* aoff, int64_t n_act_bou
                        hipStream_t st, int count_stats) {
   if (s.nc <= 64)
     hipLaunchKernelGGL(plan_small_kernel, dim3(1), dim3(64), 0, st, s, aoff, n_act_bound, target_items, count_stats,
-                       (const int32_t*)nullptr);
+                       (int32_t*)nullptr);
   else
     hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(256), 0, st, s, aoff, n_act_bound, target_items, count_stats);
   return hipGetLastError();
@@ -371,19 +329,17 @@ __device__ __forceinline__ int cluster_of_unit(const Plan* plan, int nc, int64_t
   return lo;
 }
 
-template <bool STEP>
-__global__ void __launch_bounds__(256) reduce_kernel(DevState s, const int64_t* __restrict__ aoff,
-                                                     int64_t n_bound, int n_from_aoff, double* acc, double* jerk,
-                                                     double* pot, int64_t stride) {
-  __shared__ double wave_min[256 / 64];
-  __shared__ double wave_sum[7][256 / 64];
+// The reduce work units [blockIdx.x, units) in steps of gridDim.x.  SINGLE:
+// the only cluster's plan is P1 (step pipeline); otherwise from s.plan.
+template <bool STEP, bool SINGLE>
+__device__ __forceinline__ void reduce_units(const DevState& s, int64_t units, const Plan& P1, int64_t n_active,
+                                             double* acc, double* jerk, double* pot, int64_t stride,
+                                             double* wave_min, double (*wave_sum)[256 / 64]) {
   const int tid = threadIdx.x;
-  const int64_t n_active = n_from_aoff ? aoff[s.nc] : n_bound;
-  const int64_t units = s.ctl->total_red;
   const int64_t rows_cap = s.rows_cap;
   for (int64_t u = blockIdx.x; u < units; u += gridDim.x) {
-    const int c = cluster_of_unit(s.plan, s.nc, u);
-    const Plan P = s.plan[c];
+    const int c = SINGLE ? 0 : cluster_of_unit(s.plan, s.nc, u);
+    const Plan P = SINGLE ? P1 : s.plan[c];
     const int tp = P.red_tp;
     const int epw = 256 / tp;
     const int lane = tid % tp;
@@ -468,6 +424,44 @@ __global__ void __launch_bounds__(256) reduce_kernel(DevState s, const int64_t* 
   }
 }
 
+template <bool STEP>
+__global__ void __launch_bounds__(256) reduce_kernel(DevState s, const int64_t* __restrict__ aoff,
+                                                     int64_t n_bound, int n_from_aoff, double* acc, double* jerk,
+                                                     double* pot, int64_t stride, int par, int64_t target_items) {
+  __shared__ double wave_min[256 / 64];
+  __shared__ double wave_sum[7][256 / 64];
+  const int tid = threadIdx.x;
+  const int64_t n_active = n_from_aoff ? aoff[s.nc] : n_bound;
+  // step pipeline with one cluster: the plan follows from this step's count
+  const bool single = STEP && s.nc == 1;
+  Plan P1{};
+  int64_t units;
+  if (single) {
+    P1 = plan_single(s, par, target_items);
+    units = plan_units(P1);
+  } else {
+    units = s.ctl->total_red;
+  }
+  if (single && blockIdx.x == 0 && tid == 0) {
+    // the previous step's count is read by now (force and reduction of that
+    // step, this step's selection): clear it for the next step's selection,
+    // which counts into that half; then the block-step counters
+    s.acount[par ^ 1] = 0;
+    if (P1.n_act > 0) {
+      s.inter[0] += (double)P1.n_act * (double)s.n;
+      s.steps[0] += 1;
+    }
+  }
+  if constexpr (STEP) {
+    if (single) {
+      reduce_units<true, true>(s, units, P1, n_active, acc, jerk, pot, stride, wave_min, wave_sum);
+      return;
+    }
+  }
+  reduce_units<STEP, false>(s, units, P1, n_active, acc, jerk, pot, stride, wave_min, wave_sum);
+}
+
+
 // Entries listed past the clusters' active counts (n_active larger than the
 // active offsets say) get zeros and the index status bit.
 __global__ void __launch_bounds__(256) reduce_tail_kernel(DevState s, const int64_t* __restrict__ aoff,
@@ -488,16 +482,16 @@ hipError_t launch_reduce(const DevState& s, const int64_t* aoff, int64_t n_activ
   const int64_t g = (n_active + 255) / 256;
   hipLaunchKernelGGL(reduce_tail_kernel, dim3((unsigned)g), dim3(256), 0, st, s, aoff, n_active, acc, jerk, pot);
   hipLaunchKernelGGL(reduce_kernel<false>, dim3(kReduceGrid), dim3(256), 0, st, s, aoff, n_active, 0, acc, jerk,
-                     pot, n_active);
+                     pot, n_active, -1, (int64_t)0);
   return hipGetLastError();
 }
 
-hipError_t launch_reduce_correct_step(const DevState& s, bool pot, hipStream_t st) {
+hipError_t launch_reduce_correct_step(const DevState& s, bool pot, int par, int64_t target_items, hipStream_t st) {
   // pot only flags whether the potential row exists; the step writes s.pot.
   // The active list holds each cluster's block in its own segment, so every
   // entry index is below n.
   hipLaunchKernelGGL(reduce_kernel<true>, dim3(kReduceGrid), dim3(256), 0, st, s, s.aoff, s.n, 0,
-                     (double*)nullptr, (double*)nullptr, pot ? s.pot : nullptr, (int64_t)0);
+                     (double*)nullptr, (double*)nullptr, pot ? s.pot : nullptr, (int64_t)0, par, target_items);
   return hipGetLastError();
 }
 
@@ -671,24 +665,31 @@ hipError_t launch_correct(const DevState& s, const int32_t* act, const int64_t* 
 // ---------------------------------------------------------------------------
 // Block selection (Sect. 2.1: the particles with the smallest t_i + dt_i)
 // and prediction in one kernel per block step, one workgroup per selection
-// chunk of kSelChunk particles, then the plan of the force pass.
+// chunk of kSelChunk particles, then (several clusters) the plan of the
+// force pass.
 //
 // The block time of cluster c is the minimum of t + dt over its particles.
 // It is not recomputed by a pass of its own: the previous step left it in
 // two pieces, the smallest t + dt of the particles it did not select (per
 // chunk, cm2, written here) and the smallest new t + dt of the particles it
 // corrected (per reduce unit, umin, written by the reduce kernel), and every
-// workgroup of the cluster takes the minimum of both.  cm2 is double
-// buffered (ctl->sel_parity), as this kernel reads the old and writes the
-// new values.  Members (t + dt equal to the block time; times are dyadic, so
-// the test is exact) are appended to the cluster's own segment of the
-// active list (starting at coff[c]) through an atomic counter; their order
-// there does not change any particle's sums.  Every particle of an advancing
-// cluster is predicted.  A cluster whose block time is past t_end takes no
-// step.  (Planning inside this kernel by the last workgroup to take an
-// atomic ticket was measured 70 us per step slower on a 256-cluster batch
-// than the separate launch: every workgroup then needs a device-scope fence
-// before its ticket.)
+// workgroup of the cluster takes the minimum of both.  Members (t + dt equal
+// to the block time; times are dyadic, so the test is exact) are appended to
+// the cluster's own segment of the active list (starting at coff[c]) through
+// an atomic counter; their order there does not change any particle's sums.
+// Every particle of an advancing cluster is predicted.  A cluster whose
+// block time is past t_end takes no step.
+//
+// The chunk minima (cm2) and the counters (acount) have one half per step
+// parity `par`, a launch argument that the captured graphs alternate: step k
+// reads cm2[par] and writes cm2[par ^ 1], counts into acount[par], and the
+// previous step's counts stay readable in acount[par ^ 1] until the
+// reduction of step k clears them for step k + 1.  So no kernel has to hand
+// a device-side parity on, and with a single cluster no plan kernel runs at
+// all: force and reduction derive the plan from acount[par].  (Planning
+// inside this kernel by the last workgroup to take an atomic ticket was
+// measured 70 us per step slower on a 256-cluster batch than the separate
+// launch: every workgroup then needs a device-scope fence before its ticket.)
 
 __device__ __forceinline__ double block_min(double v, double* buf) {
 #pragma unroll
@@ -703,7 +704,7 @@ __device__ __forceinline__ double block_min(double v, double* buf) {
 
 // Start of a run of steps (after the state or the plan changed outside the
 // step pipeline): cm2 = the chunk minima of t + dt, no corrected particles.
-__global__ void __launch_bounds__(kSelThreads) select_init_kernel(DevState s) {
+__global__ void __launch_bounds__(kSelThreads) select_init_kernel(DevState s, int par) {
   __shared__ double buf[kSelThreads / 64];
   const int ch = blockIdx.x;
   const int c = s.ch_cluster[ch];
@@ -712,15 +713,16 @@ __global__ void __launch_bounds__(kSelThreads) select_init_kernel(DevState s) {
   for (int64_t i = b + threadIdx.x; i < e; i += kSelThreads) mn = fmin(mn, s.t[i] + s.dt[i]);
   mn = block_min(mn, buf);
   if (threadIdx.x == 0) {
-    s.cm2[(s.ctl->sel_parity & 1) * s.nch + ch] = mn;
+    s.cm2[par * s.nch + ch] = mn;
     if (ch == s.cl_ch[c]) {
       s.plan[c].n_act = 0;
       s.acount[c] = 0;
+      s.acount[s.nc + c] = 0;
     }
   }
 }
 
-__global__ void __launch_bounds__(kSelThreads) select_kernel(DevState s, int mode) {
+__global__ void __launch_bounds__(kSelThreads) select_kernel(DevState s, int mode, int par, int64_t target_items) {
   static_assert(kSelChunk == kSelThreads, "one particle per thread");
   __shared__ double buf[kSelThreads / 64];
   __shared__ int64_t sbuf[kSelThreads / 64];
@@ -728,9 +730,8 @@ __global__ void __launch_bounds__(kSelThreads) select_kernel(DevState s, int mod
   const int ch = blockIdx.x;
   const int c = s.ch_cluster[ch];
   const int tid = threadIdx.x;
-  const int64_t par = s.ctl->sel_parity;
-  const double* cur = s.cm2 + (par & 1) * s.nch;
-  double* nxt = s.cm2 + ((par + 1) & 1) * s.nch;
+  const double* cur = s.cm2 + (int64_t)par * s.nch;
+  double* nxt = s.cm2 + (int64_t)(par ^ 1) * s.nch;
 
   // this thread's particle: its t + dt and (for a cluster that has not
   // reached the end time) the predictor's inputs do not depend on the block
@@ -750,7 +751,8 @@ __global__ void __launch_bounds__(kSelThreads) select_kernel(DevState s, int mod
   // block time of cluster c
   double mn = INFINITY;
   for (int f = s.cl_ch[c] + tid; f < s.cl_ch[c + 1]; f += kSelThreads) mn = fmin(mn, cur[f]);
-  const Plan P = s.plan[c];  // plan of the previous step
+  // plan of the previous step (the other parity)
+  const Plan P = s.nc == 1 ? plan_single(s, par ^ 1, target_items) : s.plan[c];
   if (P.n_act > 0) {
     const int64_t epw = 256 / P.red_tp;
     const int64_t units = (P.n_act + epw - 1) / epw;
@@ -767,7 +769,7 @@ __global__ void __launch_bounds__(kSelThreads) select_kernel(DevState s, int mod
   const int64_t before = wg_exclusive_scan(member ? 1 : 0, sbuf, &total);
   if (tid == 0) {
     nxt[ch] = rest;
-    base_sh = total > 0 ? atomicAdd(&s.acount[c], (int32_t)total) : 0;
+    base_sh = total > 0 ? atomicAdd(&s.acount[(int64_t)par * s.nc + c], (int32_t)total) : 0;
     if (advancing && ch == s.cl_ch[c]) s.tpred[c] = tsys;
   }
   __syncthreads();
@@ -776,25 +778,26 @@ __global__ void __launch_bounds__(kSelThreads) select_kernel(DevState s, int mod
 
 // Plan of the step's force pass from the selection counts (one workgroup),
 // then the counters and the cm2 half are handed on to the next step.
-__global__ void __launch_bounds__(256) plan_step_kernel(DevState s, int64_t target_items) {
-  plan_body(s, nullptr, s.n, target_items, 1, s.acount);
+__global__ void __launch_bounds__(256) plan_step_kernel(DevState s, int64_t target_items, int32_t* counts) {
+  plan_body(s, nullptr, s.n, target_items, 1, counts);
   __syncthreads();
-  for (int c = threadIdx.x; c < s.nc; c += 256) s.acount[c] = 0;
-  if (threadIdx.x == 0) s.ctl->sel_parity += 1;
+  for (int c = threadIdx.x; c < s.nc; c += 256) counts[c] = 0;  // read: cleared for the step after next
 }
 
-hipError_t launch_select_init(const DevState& s, hipStream_t st) {
-  hipLaunchKernelGGL(select_init_kernel, dim3(s.nch), dim3(kSelThreads), 0, st, s);
+hipError_t launch_select_init(const DevState& s, int par, hipStream_t st) {
+  hipLaunchKernelGGL(select_init_kernel, dim3(s.nch), dim3(kSelThreads), 0, st, s, par);
   return hipGetLastError();
 }
 
-hipError_t launch_select(const DevState& s, int64_t target_items, int mode, hipStream_t st) {
-  hipLaunchKernelGGL(select_kernel, dim3(s.nch), dim3(kSelThreads), 0, st, s, mode);
+hipError_t launch_select(const DevState& s, int64_t target_items, int mode, int par, hipStream_t st) {
+  hipLaunchKernelGGL(select_kernel, dim3(s.nch), dim3(kSelThreads), 0, st, s, mode, par, target_items);
+  if (s.nc == 1) return hipGetLastError();  // the force and reduce kernels plan for themselves
+  int32_t* counts = s.acount + (int64_t)par * s.nc;
   if (s.nc <= 64)
     hipLaunchKernelGGL(plan_small_kernel, dim3(1), dim3(64), 0, st, s, (const int64_t*)nullptr, s.n, target_items,
-                       1, (const int32_t*)s.acount);
+                       1, counts);
   else
-    hipLaunchKernelGGL(plan_step_kernel, dim3(1), dim3(256), 0, st, s, target_items);
+    hipLaunchKernelGGL(plan_step_kernel, dim3(1), dim3(256), 0, st, s, target_items, counts);
   return hipGetLastError();
 }
 
