@@ -29,7 +29,7 @@ constexpr uint32_t kStateVersion = 1;
 struct Layout {
   size_t coff, eps, cid, ch_cluster, ch_begin, cl_ch;
   size_t m, x, v, a, k, t, dt, xp, vp, pot, jr;
-  size_t tpred, tnow, inter, steps, cm2, acount, umin, act, aoff, plan, ctl, part, fout, status, eout;
+  size_t tpred, tnow, inter, steps, cm2, acount, umin, act, aoff, plan, offs, ctl, part, fout, status, eout;
   size_t total;
   int64_t rows_cap;
   int64_t nch_max;
@@ -75,6 +75,7 @@ Layout make_layout(int64_t n, int32_t nc) {
   L.act = take(4 * N);
   L.aoff = take(8 * (C + 1));
   L.plan = take(sizeof(Plan) * C);
+  L.offs = take(16 * C);
   L.ctl = take(sizeof(Ctl));
   L.part = take(8 * 7 * (size_t)L.rows_cap);
   L.fout = take(8 * 7 * N);
@@ -372,6 +373,7 @@ nbody_status nbody_init(nbody_ctx** out, int64_t n_total, int32_t n_clusters, co
   s.act = (int32_t*)(w + L.act);
   s.aoff = (int64_t*)(w + L.aoff);
   s.plan = (Plan*)(w + L.plan);
+  s.offs = (int64_t*)(w + L.offs);
   s.ctl = (Ctl*)(w + L.ctl);
   s.part = (double*)(w + L.part);
   s.rows_cap = L.rows_cap;

@@ -19,6 +19,9 @@ enum : int32_t {
   ST_STATE = 8,      // corrector asked to step by a non-positive time, or a force work item of a layout the launched kernel lacks
 };
 
+// Batches of up to this many clusters look up the cluster of a work item in
+// a copy of the plan offsets in LDS.
+constexpr int kLdsClusters = 1024;
 // Threads per workgroup of every force launch; the i x j layout of a
 // workgroup is (256 / JL) i-slots times JL j-lanes.
 constexpr int kForceThreads = 256;
@@ -111,6 +114,7 @@ struct DevState {
   int32_t* act;    // [n] active list (step pipeline: cluster c's block at act[coff[c]...])
   int64_t* aoff;   // [nc+1] active offsets of the internal all-particle passes
   Plan* plan;      // [nc]
+  int64_t* offs;   // [2][nc] item_off and red_off of the plan, contiguous (cluster lookup in LDS)
   Ctl* ctl;
   double* part;    // [7][rows_cap] partial sums
   int64_t rows_cap;
@@ -177,6 +181,16 @@ __device__ inline Plan plan_single(const DevState& s, int par, int64_t target_it
   Plan P{};
   plan_layout(s.acount[par], s.n, target_items, vmin_all, P);
   return P;
+}
+
+// Index of the last of the nc ascending offsets that is <= x (offs[0] = 0).
+__device__ inline int last_at_or_below(const int64_t* offs, int nc, int64_t x) {
+  int lo = 0, hi = nc - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (offs[mid] <= x) lo = mid; else hi = mid - 1;
+  }
+  return lo;
 }
 
 }  // namespace nb

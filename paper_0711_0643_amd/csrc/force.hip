@@ -555,7 +555,14 @@ __global__ void __launch_bounds__(kForceThreads) __attribute__((amdgpu_waves_per
 force_kernel(DevState s, const int32_t* __restrict__ act, int par, int64_t target_items) {
   __shared__ __attribute__((aligned(16))) unsigned char lds[kLdsBytes];
   __shared__ float wmax[kTile / 32];
+  __shared__ int64_t offs_sh[kLdsClusters];
   const bool single = par >= 0 && s.nc == 1;
+  // batches of up to kLdsClusters: the item offsets in LDS for the lookup
+  const bool lds_lookup = !single && s.nc > 1 && s.nc <= kLdsClusters;
+  if (lds_lookup) {
+    for (int k = threadIdx.x; k < s.nc; k += kForceThreads) offs_sh[k] = s.offs[k];
+    __syncthreads();
+  }
   Plan P1{};
   int64_t total;
   if (single) {
@@ -565,7 +572,7 @@ force_kernel(DevState s, const int32_t* __restrict__ act, int par, int64_t targe
     total = s.ctl->total_items;
   }
   for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
-    const int c = single ? 0 : find_cluster(s.plan, s.nc, item);
+    const int c = single ? 0 : lds_lookup ? last_at_or_below(offs_sh, s.nc, item) : find_cluster(s.plan, s.nc, item);
     const Plan P = single ? P1 : s.plan[c];
     const int64_t local = item - P.item_off;
     if constexpr (SPLIT) {

@@ -200,6 +200,8 @@ __device__ void plan_body(const DevState& s, const int64_t* __restrict__ aoff, i
     P.item_off = bi;
     P.slot_base = br;
     P.red_off = bu;
+    s.offs[c] = bi;
+    s.offs[nc + c] = bu;
     bi += (int64_t)P.chunks * P.slices;
     br += (int64_t)P.slices * P.n_act;
     bu += plan_units(P);
@@ -247,7 +249,11 @@ __device__ void plan_small(const DevState& s, const int64_t* __restrict__ aoff, 
   P.item_off = wave_exclusive_scan(c < nc ? (int64_t)P.chunks * P.slices : 0, &tot_items);
   P.slot_base = wave_exclusive_scan(c < nc ? (int64_t)P.slices * P.n_act : 0, &tot_rows);
   P.red_off = wave_exclusive_scan(c < nc ? plan_units(P) : 0, &tot_red);
-  if (c < nc) s.plan[c] = P;
+  if (c < nc) {
+    s.plan[c] = P;
+    s.offs[c] = P.item_off;
+    s.offs[nc + c] = P.red_off;
+  }
   if (c == 0) {
     if (tot_rows > s.rows_cap) {  // cannot happen with the bounds of the plan; refuse the pass
       set_status(s, ST_INDEX);
@@ -334,11 +340,17 @@ __device__ __forceinline__ int cluster_of_unit(const Plan* plan, int nc, int64_t
 template <bool STEP, bool SINGLE>
 __device__ __forceinline__ void reduce_units(const DevState& s, int64_t units, const Plan& P1, int64_t n_active,
                                              double* acc, double* jerk, double* pot, int64_t stride,
-                                             double* wave_min, double (*wave_sum)[256 / 64]) {
+                                             double* wave_min, double (*wave_sum)[256 / 64], int64_t* offs_sh) {
   const int tid = threadIdx.x;
   const int64_t rows_cap = s.rows_cap;
+  // batches of up to kLdsClusters: the unit offsets in LDS for the lookup
+  const bool lds_lookup = !SINGLE && s.nc > 1 && s.nc <= kLdsClusters;
+  if (lds_lookup) {
+    for (int k = tid; k < s.nc; k += 256) offs_sh[k] = s.offs[s.nc + k];
+    __syncthreads();
+  }
   for (int64_t u = blockIdx.x; u < units; u += gridDim.x) {
-    const int c = SINGLE ? 0 : cluster_of_unit(s.plan, s.nc, u);
+    const int c = SINGLE ? 0 : lds_lookup ? last_at_or_below(offs_sh, s.nc, u) : cluster_of_unit(s.plan, s.nc, u);
     const Plan P = SINGLE ? P1 : s.plan[c];
     const int tp = P.red_tp;
     const int epw = 256 / tp;
@@ -430,6 +442,7 @@ __global__ void __launch_bounds__(256) reduce_kernel(DevState s, const int64_t* 
                                                      double* pot, int64_t stride, int par, int64_t target_items) {
   __shared__ double wave_min[256 / 64];
   __shared__ double wave_sum[7][256 / 64];
+  __shared__ int64_t offs_sh[kLdsClusters];
   const int tid = threadIdx.x;
   const int64_t n_active = n_from_aoff ? aoff[s.nc] : n_bound;
   // step pipeline with one cluster: the plan follows from this step's count
@@ -454,11 +467,11 @@ __global__ void __launch_bounds__(256) reduce_kernel(DevState s, const int64_t* 
   }
   if constexpr (STEP) {
     if (single) {
-      reduce_units<true, true>(s, units, P1, n_active, acc, jerk, pot, stride, wave_min, wave_sum);
+      reduce_units<true, true>(s, units, P1, n_active, acc, jerk, pot, stride, wave_min, wave_sum, offs_sh);
       return;
     }
   }
-  reduce_units<STEP, false>(s, units, P1, n_active, acc, jerk, pot, stride, wave_min, wave_sum);
+  reduce_units<STEP, false>(s, units, P1, n_active, acc, jerk, pot, stride, wave_min, wave_sum, offs_sh);
 }
 
 
