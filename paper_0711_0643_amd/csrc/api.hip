@@ -693,6 +693,10 @@ nbody_status nbody_set_tuning(nbody_ctx* c, const nbody_tuning* t) {
   for (int i = 0; i < kNumVariants - 1; ++i) c->ctl.vmin_small[i] = t->small_min_block[i];
   c->ctl.small_n = t->small_cluster_n;
   destroy_graph(c);  // the captured step bakes in grid, plan target and format
+  // the step pipeline's carried-over state (with one cluster, the previous
+  // step's plan is recomputed from its count) assumes the plan settings it
+  // was made with: rebuild it at the next step
+  c->sel_valid = false;
   const nbody_status r = upload_ctl(c);
   if (r == NBODY_OK && recal) HIP_OK(launch_rsq_bias(c->s, c->rsq_correct, c->stream));
   return r;

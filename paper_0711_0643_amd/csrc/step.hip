@@ -790,7 +790,7 @@ __global__ void __launch_bounds__(kSelThreads) select_kernel(DevState s, int mod
 }
 
 // Plan of the step's force pass from the selection counts (one workgroup),
-// then the counters and the cm2 half are handed on to the next step.
+// then this parity's counters are cleared for the step after next.
 __global__ void __launch_bounds__(256) plan_step_kernel(DevState s, int64_t target_items, int32_t* counts) {
   plan_body(s, nullptr, s.n, target_items, 1, counts);
   __syncthreads();

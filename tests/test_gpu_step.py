@@ -204,6 +204,39 @@ def test_step_calls_of_any_length_give_the_same_run(clusters):
     sim.close()
 
 
+@pytest.mark.parametrize("clusters", [1, 3], ids=["one_cluster", "three_clusters"])
+def test_tuning_change_between_step_calls(clusters):
+    """A run whose slicing target and layout thresholds change between two
+    step calls continues exactly as a run restarted from a checkpoint with
+    the new tuning (the carried-over selection state must not assume the
+    old plan)."""
+    if clusters == 1:
+        m, x, v = icgen.plummer(4096, 62)
+        eps, coff = 1.0 / 4096, None
+    else:
+        m, x, v, coff, eps = icgen.ensemble(3, 16, 300, 900)
+    banner(f"tuning change, {clusters} cluster(s)")
+    # fewer j-slices per block (so the reduction's units change) and other layouts
+    new = dict(target_items=8, min_block=[8192, 8192, 8, 2], small_cluster_n=0)
+    a = _sim(m, x, v, eps, precision=1, coff=coff)
+    a.step(45, 0.5)
+    blob = a.get_state()
+    a.set_tuning(**new)
+    a.step(60, 0.5)
+    b = _sim(m, x, v, eps, precision=1, coff=coff)
+    b.set_state(blob)
+    b.set_tuning(**new)
+    b.step(60, 0.5)
+    sa, sb = a.host_state(), b.host_state()
+    assert a.status() == 0 and b.status() == 0
+    for key in sa:
+        assert np.array_equal(sa[key], sb[key]), key
+    for u, w in zip(a.progress(), b.progress()):
+        assert np.array_equal(u, w)
+    a.close()
+    b.close()
+
+
 def test_batched_clusters_match_single_runs():
     """Four clusters advanced together: every cluster is bit-identical to the
     same cluster integrated alone (plans depend only on a cluster's own sizes)."""
