@@ -151,8 +151,8 @@ NBODY_API nbody_status nbody_correct(nbody_ctx *ctx, const int32_t *active_idx,
  * with the smallest t_i + dt_i, predict all, force on the block, correct,
  * new steps).  Each step advances every cluster whose time is below t_end by
  * exactly one of its own block steps; clusters at t_end stay put.  t_end
- * must be a multiple of dt_max.  Runs as a captured HIP graph, replayed
- * n_block_steps times without host synchronisation. */
+ * must be a multiple of dt_max.  Runs as captured HIP graphs (runs of 32
+ * steps and single steps), replayed without host synchronisation. */
 NBODY_API nbody_status nbody_step(nbody_ctx *ctx, int32_t n_block_steps, double t_end);
 
 /* Waits for the context's stream; returns the first device-side error. */
