@@ -216,17 +216,23 @@ def test_tuning_change_between_step_calls(clusters):
     else:
         m, x, v, coff, eps = icgen.ensemble(3, 16, 300, 900)
     banner(f"tuning change, {clusters} cluster(s)")
-    # fewer j-slices per block (so the reduction's units change) and other layouts
+    # fewer j-slices per block (so the reduction's units change) and other
+    # layouts; the change comes right after the block at t = 1/8, where every
+    # particle is active, so the carried-over state spans many reduce units
     new = dict(target_items=8, min_block=[8192, 8192, 8, 2], small_cluster_n=0)
+    probe = _sim(m, x, v, eps, precision=1, coff=coff)
+    probe.run(0.125)
+    k = int(probe.progress()[1].max())  # replays up to and including the block at t = 1/8
+    probe.close()
     a = _sim(m, x, v, eps, precision=1, coff=coff)
-    a.step(45, 0.5)
+    a.step(k, 0.125)
     blob = a.get_state()
     a.set_tuning(**new)
-    a.step(60, 0.5)
+    a.step(60, 0.25)
     b = _sim(m, x, v, eps, precision=1, coff=coff)
     b.set_state(blob)
     b.set_tuning(**new)
-    b.step(60, 0.5)
+    b.step(60, 0.25)
     sa, sb = a.host_state(), b.host_state()
     assert a.status() == 0 and b.status() == 0
     for key in sa:
