@@ -128,23 +128,27 @@ struct DevState {
 // j-slices as bring the cluster alone to about target_items work items, at
 // most one per LDS tile and at most what the cluster's partial-row budget
 // allows.  Offsets (item_off, slot_base, act_off, red_off) are not set.
-__device__ inline void plan_layout(int64_t na, int64_t nn, int64_t target_items, const int32_t* vmin_all, Plan& P) {
-  const int32_t* vmin = nn < (int64_t)vmin_all[2 * (kNumVariants - 1)] ? vmin_all + (kNumVariants - 1) : vmin_all;
+// Integer type T: every intermediate fits in it (32-bit divisions are much
+// shorter than 64-bit ones, and this runs in kernel prologues).
+template <typename T>
+__device__ inline void plan_layout_t(T na, T nn, T target_items, const int32_t* vmin_all, Plan& P) {
+  const int32_t* vmin = (int64_t)nn < (int64_t)vmin_all[2 * (kNumVariants - 1)] ? vmin_all + (kNumVariants - 1)
+                                                                                   : vmin_all;
   int var = kNumVariants - 1;
   for (int vv = kNumVariants - 2; vv >= 0; --vv)
-    if (na >= vmin[vv]) var = vv;
-  const int64_t iwg = variant_iwg(var);
-  const int64_t chunks = (na + iwg - 1) / iwg;
-  int64_t S = 1;
+    if ((int64_t)na >= vmin[vv]) var = vv;
+  const T iwg = (T)variant_iwg(var);
+  const T chunks = (na + iwg - 1) / iwg;
+  T S = 1;
   if (chunks > 0) {
-    const int64_t smax_tiles = (nn + kTile - 1) / kTile;
-    const int64_t smax_rows = (kRowsPerParticle * nn + kRowsPerCluster) / na;
+    const T smax_tiles = (nn + kTile - 1) / kTile;
+    const T smax_rows = ((T)kRowsPerParticle * nn + (T)kRowsPerCluster) / na;
     S = (target_items + chunks - 1) / chunks;
     if (S > smax_tiles) S = smax_tiles;
     if (S > smax_rows) S = smax_rows;
     if (S < 1) S = 1;
   }
-  int64_t slen = (nn + S - 1) / S;
+  T slen = (nn + S - 1) / S;
   slen = (slen + kTile - 1) / kTile * kTile;
   S = (nn + slen - 1) / slen;
   P.n_act = (int32_t)na;
@@ -153,8 +157,17 @@ __device__ inline void plan_layout(int64_t na, int64_t nn, int64_t target_items,
   P.slices = (int32_t)S;
   P.slice_len = (int32_t)slen;
   int tp = 1;  // reduce lanes per entry
-  while (tp < S && tp < 256) tp <<= 1;
+  while ((T)tp < S && tp < 256) tp <<= 1;
   P.red_tp = tp;
+}
+
+__device__ inline void plan_layout(int64_t na, int64_t nn, int64_t target_items, const int32_t* vmin_all, Plan& P) {
+  // 32-bit when kRowsPerParticle * nn + kRowsPerCluster and every other
+  // intermediate stays below 2^32
+  if (nn < ((int64_t)1 << 26) && target_items < ((int64_t)1 << 30))
+    plan_layout_t<uint32_t>((uint32_t)na, (uint32_t)nn, (uint32_t)target_items, vmin_all, P);
+  else
+    plan_layout_t<int64_t>(na, nn, target_items, vmin_all, P);
 }
 
 __device__ inline void load_thresholds(const Ctl* ctl, int32_t* vmin_all) {
