@@ -71,20 +71,25 @@ def calibrate_copy():
     print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "copies": 5}), flush=True)
 
 
+# the sources the force kernel is compiled from
+FORCE_SOURCES = ("force.hip", "common.h", "kernels.h")
+
+
 def recorded_traffic():
     """HBM bytes per launch of the mixed force kernel from the committed
-    rocprofv3 counter summary -- only if force.hip is the source that was
-    profiled (else None)."""
+    rocprofv3 counter summary -- only if the force kernel's sources are the
+    ones that were profiled (else None)."""
     import hashlib
 
-    src = os.path.join(ROOT, "paper_0711_0643_amd", "csrc", "force.hip")
     prof = os.path.join(ROOT, "profiles", "force_mixed_n65536_hbm_counters.txt")
     try:
         text = open(prof).read()
-        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        for name in FORCE_SOURCES:
+            src = os.path.join(ROOT, "paper_0711_0643_amd", "csrc", name)
+            digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+            if f"{name} sha256: {digest}" not in text:
+                return None
     except OSError:
-        return None
-    if f"force.hip sha256: {digest}" not in text:
         return None
     for line in text.splitlines():
         if line.startswith("traffic_bytes_per_launch:"):
