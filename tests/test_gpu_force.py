@@ -337,6 +337,33 @@ def test_king_salpeter_n262144_full_block_sampled(precision):
     sim.close()
 
 
+def test_plummer_n1048576_sampled():
+    """The largest single cluster tested: Plummer N = 2^20, eps = 1/N, a
+    block of 4096 active particles (2 i per lane, 1024 tiles per slice row);
+    256 seeded entries of it against the oracle, one by one, in both
+    precisions, plus a few block steps that must stay error free."""
+    n = 1 << 20
+    m, x, v = icgen.plummer(n, 8)
+    eps = 1.0 / n
+    act = icgen.active_subset(n, 4096, seed=11)
+    pick = np.sort(np.random.default_rng(4).choice(act.size, 256, replace=False))
+    sample = act[pick]
+    ref = oracle.force(m, x, v, eps, sample)
+    absum = oracle.force_abs(m, x, v, eps, sample)
+    for precision in (0, 1):
+        banner(f"Plummer N={n} block 4096 precision={precision}")
+        sim = _sim(m, x, v, eps, precision)
+        got = _gpu_force(sim, act)
+        part = (got[0][:, pick], got[1][:, pick], got[2][pick])
+        if precision == 0:
+            _check_fp64(part, ref)
+        else:
+            _check_mixed(part, ref, absum)
+        sim.step(3, 0.125)
+        assert sim.status() == 0
+        sim.close()
+
+
 @pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
 def test_batch_of_256_clusters_ragged_blocks(precision):
     """The 256-cluster batch (N log-uniform in [256, 8192], sum 673038), a
