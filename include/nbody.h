@@ -92,7 +92,7 @@ NBODY_API void nbody_default_params(nbody_params *p);
 
 /* Bytes of device workspace needed for n_total particles in n_clusters
  * clusters.  Pure host computation; never fails for valid sizes
- * (n_total >= 1, 1 <= n_clusters <= n_total, n_total < 2^31). */
+ * (n_total >= 1, 1 <= n_clusters <= n_total, n_total <= 2^30). */
 NBODY_API nbody_status nbody_workspace_bytes(int64_t n_total, int32_t n_clusters, const nbody_params *p,
                                    size_t *bytes);
 

@@ -282,7 +282,7 @@ void nbody_default_params(nbody_params* p) {
 
 nbody_status nbody_workspace_bytes(int64_t n_total, int32_t n_clusters, const nbody_params* p, size_t* bytes) {
   (void)p;
-  if (!bytes || n_total < 1 || n_total >= ((int64_t)1 << 31) - 1 || n_clusters < 1 || n_clusters > n_total)
+  if (!bytes || n_total < 1 || n_total > kMaxParticles || n_clusters < 1 || n_clusters > n_total)
     return NBODY_E_INVAL;
   *bytes = make_layout(n_total, n_clusters).total;
   return NBODY_OK;
@@ -294,7 +294,7 @@ nbody_status nbody_init(nbody_ctx** out, int64_t n_total, int32_t n_clusters, co
   if (!out) return NBODY_E_INVAL;
   *out = nullptr;
   if (!cluster_offsets || !m || !x || !v || !eps || !workspace || !valid_params(p)) return NBODY_E_INVAL;
-  if (n_total < 1 || n_total >= ((int64_t)1 << 31) - 1 || n_clusters < 1 || n_clusters > n_total)
+  if (n_total < 1 || n_total > kMaxParticles || n_clusters < 1 || n_clusters > n_total)
     return NBODY_E_INVAL;
   if (((uintptr_t)workspace & 255) != 0) return NBODY_E_INVAL;
   if (cluster_offsets[0] != 0 || cluster_offsets[n_clusters] != n_total) return NBODY_E_INVAL;

@@ -27,6 +27,10 @@ constexpr int kLdsClusters = 1024;
 constexpr int kForceThreads = 256;
 // j-records staged in LDS per tile.
 constexpr int kTile = 256;
+// Largest total particle count: keeps every per-cluster count and slice
+// length of the plan (int32) far from overflow.  (The workspace of that many
+// particles, mostly partial rows, would exceed any GPU's memory anyway.)
+constexpr int64_t kMaxParticles = (int64_t)1 << 30;
 // Largest slicing target a plan may be asked for.
 constexpr int64_t kMaxTargetItems = 16384;
 // Partial-row budget: a cluster of N particles may use up to
@@ -53,7 +57,7 @@ struct Plan {
   int32_t variant;    // i x j layout (index into variant_jl)
   int32_t chunks;     // i-chunks of variant_iwg(variant) active particles
   int32_t slices;     // j-slices
-  int32_t slice_len;  // j per slice (multiple of kTile)
+  int32_t slice_len;  // j per slice (multiple of kTile; clusters hold at most kMaxParticles)
   int32_t red_tp;     // reduce: lanes per entry (power of two, <= 256)
   int64_t red_off;    // reduce: first work unit of this cluster
 };
@@ -131,7 +135,7 @@ struct DevState {
 // Integer type T: every intermediate fits in it (32-bit divisions are much
 // shorter than 64-bit ones, and this runs in kernel prologues).
 template <typename T>
-__device__ inline void plan_layout_t(T na, T nn, T target_items, const int32_t* vmin_all, Plan& P) {
+__host__ __device__ inline void plan_layout_t(T na, T nn, T target_items, const int32_t* vmin_all, Plan& P) {
   const int32_t* vmin = (int64_t)nn < (int64_t)vmin_all[2 * (kNumVariants - 1)] ? vmin_all + (kNumVariants - 1)
                                                                                    : vmin_all;
   int var = kNumVariants - 1;
@@ -161,7 +165,8 @@ __device__ inline void plan_layout_t(T na, T nn, T target_items, const int32_t* 
   P.red_tp = tp;
 }
 
-__device__ inline void plan_layout(int64_t na, int64_t nn, int64_t target_items, const int32_t* vmin_all, Plan& P) {
+__host__ __device__ inline void plan_layout(int64_t na, int64_t nn, int64_t target_items, const int32_t* vmin_all,
+                                            Plan& P) {
   // 32-bit when kRowsPerParticle * nn + kRowsPerCluster and every other
   // intermediate stays below 2^32
   if (nn < ((int64_t)1 << 26) && target_items < ((int64_t)1 << 30))
@@ -180,8 +185,9 @@ __device__ inline void load_thresholds(const Ctl* ctl, int32_t* vmin_all) {
 }
 
 // Reduce work units of a cluster's plan.
-__device__ inline int64_t plan_units(const Plan& P) {
-  return (P.n_act + (256 / P.red_tp) - 1) / (256 / P.red_tp);
+__host__ __device__ inline int64_t plan_units(const Plan& P) {
+  const int64_t epw = 256 / P.red_tp;  // entries per unit
+  return ((int64_t)P.n_act + epw - 1) / epw;
 }
 
 // The plan of the step pipeline when there is a single cluster: its block

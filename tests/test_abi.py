@@ -67,6 +67,9 @@ def test_workspace_bytes_validation():
     assert L.nbody_workspace_bytes(10, 0, ctypes.byref(p), ctypes.byref(sz)) == -1
     assert L.nbody_workspace_bytes(10, 11, ctypes.byref(p), ctypes.byref(sz)) == -1
     assert L.nbody_workspace_bytes(1 << 31, 1, ctypes.byref(p), ctypes.byref(sz)) == -1
+    # the particle limit, 2^30: accepted at the limit, rejected above it
+    assert L.nbody_workspace_bytes(1 << 30, 1, ctypes.byref(p), ctypes.byref(sz)) == 0 and sz.value > 0
+    assert L.nbody_workspace_bytes((1 << 30) + 1, 1, ctypes.byref(p), ctypes.byref(sz)) == -1
 
 
 def _init(n=8, nc=1, coff=None, eps=None, ws_bytes=1 << 30, workspace=256, params=None, **pk):
