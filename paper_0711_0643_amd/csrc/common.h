@@ -31,6 +31,8 @@ constexpr int kTile = 256;
 // length of the plan (int32) far from overflow.  (The workspace of that many
 // particles, mostly partial rows, would exceed any GPU's memory anyway.)
 constexpr int64_t kMaxParticles = (int64_t)1 << 30;
+// Blocks of at least this many entries are reduced with one lane per entry.
+constexpr int64_t kReduceSerialBlock = 2048;
 // Largest slicing target a plan may be asked for.
 constexpr int64_t kMaxTargetItems = 16384;
 // Partial-row budget: a cluster of N particles may use up to
@@ -160,8 +162,13 @@ __host__ __device__ inline void plan_layout_t(T na, T nn, T target_items, const 
   P.chunks = (int32_t)chunks;
   P.slices = (int32_t)S;
   P.slice_len = (int32_t)slen;
-  int tp = 1;  // reduce lanes per entry
-  while ((T)tp < S && tp < 256) tp <<= 1;
+  // reduce lanes per entry: for small blocks as many as there are slices
+  // (summed in parallel, then by a tree); for large blocks one lane per
+  // entry, which adds its slices in turn with coalesced loads and runs its
+  // entry's corrector itself (no lanes idle during the corrector)
+  int tp = 1;
+  if ((int64_t)na < kReduceSerialBlock)
+    while ((T)tp < S && tp < 256) tp <<= 1;
   P.red_tp = tp;
 }
 

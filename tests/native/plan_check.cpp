@@ -53,7 +53,8 @@ int main() {
           if ((int64_t)P.slices * na > kRowsPerParticle * nn + kRowsPerCluster)
             return fail("partial rows over budget", na, nn, tgt);
           if (P.red_tp < 1 || P.red_tp > 256 || (P.red_tp & (P.red_tp - 1)) != 0 ||
-              (P.red_tp < 256 && P.red_tp < P.slices))
+              (na < kReduceSerialBlock && P.red_tp < 256 && P.red_tp < P.slices) ||
+              (na >= kReduceSerialBlock && P.red_tp != 1))
             return fail("reduce lanes", na, nn, tgt);
           const int64_t epw = 256 / P.red_tp;
           if (plan_units(P) * epw < na || (na > 0 && (plan_units(P) - 1) * epw >= na))
