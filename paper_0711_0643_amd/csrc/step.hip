@@ -753,6 +753,15 @@ __global__ void __launch_bounds__(kSelThreads) select_kernel(DevState s, int mod
   const int64_t i = s.ch_begin[ch] + tid;
   const bool have = i < s.ch_begin[ch + 1];
   const bool ahead = s.tnow[c] < s.ctl->t_end;
+  // plan of the previous step (the other parity)
+  const Plan P = s.nc == 1 ? plan_single(s, par ^ 1, target_items) : s.plan[c];
+  if (!ahead && P.n_act == 0) {
+    // the cluster has reached the end time (so it takes no step: every
+    // particle is at t_end) and took none last step either: the chunk's
+    // minimum of t + dt is unchanged, nothing else to do
+    if (tid == 0) nxt[ch] = cur[ch];
+    return;
+  }
   double tt = INFINITY;
   PredIn pin{};
   if (have) {
@@ -764,8 +773,6 @@ __global__ void __launch_bounds__(kSelThreads) select_kernel(DevState s, int mod
   // block time of cluster c
   double mn = INFINITY;
   for (int f = s.cl_ch[c] + tid; f < s.cl_ch[c + 1]; f += kSelThreads) mn = fmin(mn, cur[f]);
-  // plan of the previous step (the other parity)
-  const Plan P = s.nc == 1 ? plan_single(s, par ^ 1, target_items) : s.plan[c];
   if (P.n_act > 0) {
     const int64_t epw = 256 / P.red_tp;
     const int64_t units = (P.n_act + epw - 1) / epw;
