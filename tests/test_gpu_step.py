@@ -266,6 +266,38 @@ def test_batched_clusters_match_single_runs():
     both.close()
 
 
+def test_finished_batch_idles_then_continues():
+    """Clusters of a batch that have reached the end time take no step: more
+    step calls leave every bit of the state and the step counts alone, and a
+    later call with a larger end time carries on exactly as a run that never
+    stopped (t = 1/4 is a multiple of dt_max = 1/8, so every particle lands on
+    it in both runs)."""
+    m, x, v, coff, eps = icgen.ensemble(5, 21, 64, 700)
+    banner("finished batch idles then continues")
+    sim = _sim(m, x, v, eps, coff=coff)
+    sim.run(0.25, chunk=64)
+    a = sim.host_state()
+    pa = [np.array(u, copy=True) for u in sim.progress()]
+    assert np.all(pa[0] == 0.25)
+    for n_steps in (1, 7, 64):
+        sim.step(n_steps, 0.25)
+    b = sim.host_state()
+    for key in a:
+        assert np.array_equal(a[key], b[key]), key
+    for u, w in zip(pa, sim.progress()):
+        assert np.array_equal(u, w)
+    sim.run(0.5, chunk=64)
+    ref = _sim(m, x, v, eps, coff=coff)
+    ref.run(0.5, chunk=64)
+    c, d = sim.host_state(), ref.host_state()
+    for key in c:
+        assert np.array_equal(c[key], d[key]), key
+    for u, w in zip(sim.progress(), ref.progress()):
+        assert np.array_equal(u, w)
+    sim.close()
+    ref.close()
+
+
 def test_status_reports_step_underflow():
     """Two bodies 1e-9 apart with no softening need steps far below dt_min = 2^-20."""
     m = np.array([0.5, 0.5])
