@@ -173,6 +173,133 @@ def pin_active_subset_matches_full():
     assert np.array_equal(p_s, p_all[act])
 
 
+# --------------------------------------------------------------------------
+# Sums of absolute pair terms (the error scale of the force gates): closed
+# forms and the triangle inequality, with equality where every term points
+# the same way.
+
+def pin_force_abs_two_body():
+    """One pair, r = (d, 0, 0), relative velocity (u, w, 0): the acceleration
+    term has length m d / R^3, the jerk term is m/R^3 (u (1 - 3 d^2/R^2), w, 0)
+    and the potential term m / R, with R^2 = d^2 + eps^2."""
+    d, u, w, m1, m2, eps = 1.25, 0.5, -0.75, 0.375, 0.625, 0.2
+    m = np.array([m1, m2])
+    x = np.array([[0.5, 0.5 + d], [0.25, 0.25], [0.0, 0.0]])
+    v = np.array([[0.125, 0.125 + u], [1.0, 1.0 + w], [-0.5, -0.5]])
+    out = oracle.force_abs(m, x, v, eps)
+    R2 = d * d + eps * eps
+    R3 = R2**1.5
+    for i, mj in ((0, m2), (1, m1)):
+        assert abs(out[0, i] - mj * d / R3) < 1e-15 * mj * d / R3
+        kj = mj / R3 * math.hypot(u * (1 - 3 * d * d / R2), w)
+        assert abs(out[1, i] - kj) < 1e-14 * kj
+        assert abs(out[2, i] - mj / math.sqrt(R2)) < 1e-15 * mj / math.sqrt(R2)
+
+
+def pin_force_abs_rotating_ring():
+    """Rigid rotation at rate omega: every relative velocity is omega z x r,
+    perpendicular to r with length omega |r|, so each jerk term has length
+    omega times its acceleration term and the jerk sum is omega times the
+    acceleration sum, sum_k m c_k / (c_k^2 + eps^2)^1.5 with chords
+    c_k = 2 R sin(pi k / n); the potential sum is sum_k m / sqrt(c_k^2 + eps^2)."""
+    for n, eps in ((9, 0.0), (16, 0.1)):
+        R, om, mm = 0.8, 1.3, 1.0 / n
+        m, x, v, _ = _ring(n, R, om, mm)
+        out = oracle.force_abs(m, x, v, eps)
+        ck = 2 * R * np.sin(math.pi * np.arange(1, n) / n)
+        sa = np.sum(mm * ck / (ck**2 + eps * eps) ** 1.5)
+        sp = np.sum(mm / np.sqrt(ck**2 + eps * eps))
+        assert _rel(out[0], np.full(n, sa)) < 1e-14
+        assert _rel(out[1], np.full(n, om * sa)) < 1e-13
+        assert _rel(out[2], np.full(n, sp)) < 1e-14
+
+
+def pin_force_abs_collinear_equality():
+    """Particle 0 at the end of a line of particles on the x axis, all others
+    receding along the line (u_j > u_0): every acceleration term points along
+    +x and (for |r| > eps / sqrt 2) every jerk term along -x, so the sums of
+    term lengths equal the lengths of the sums; every potential term is
+    negative, so the potential sum is -phi."""
+    rng = np.random.Generator(np.random.PCG64(31))
+    n, eps = 12, 0.05
+    m = rng.random(n) + 0.1
+    x = np.zeros((3, n))
+    x[0] = np.concatenate([[0.0], np.sort(rng.random(n - 1)) * 3 + 0.2])
+    v = np.zeros((3, n))
+    v[0] = np.concatenate([[-0.3], rng.random(n - 1) + 0.05])
+    acc, jerk, pot = oracle.force(m, x, v, eps)
+    out = oracle.force_abs(m, x, v, eps)
+    assert abs(out[0, 0] - np.linalg.norm(acc[:, 0])) < 1e-14 * out[0, 0]
+    assert abs(out[1, 0] - np.linalg.norm(jerk[:, 0])) < 1e-14 * out[1, 0]
+    assert _rel(out[2], -pot) < 1e-14
+
+
+def pin_force_abs_bounds():
+    """Triangle inequality on a random system: |a_i| <= A_i, |k_i| <= K_i, and
+    the potential sum is -phi_i (all terms of one sign)."""
+    m, x, v = _random_system(80, 17)
+    acc, jerk, pot = oracle.force(m, x, v, 0.03)
+    out = oracle.force_abs(m, x, v, 0.03)
+    assert np.all(np.linalg.norm(acc, axis=0) <= out[0] * (1 + 1e-14))
+    assert np.all(np.linalg.norm(jerk, axis=0) <= out[1] * (1 + 1e-14))
+    assert _rel(out[2], -pot) < 1e-14
+    # and the bound is not slack everywhere: cancellation is partial
+    assert np.min(out[0] / np.linalg.norm(acc, axis=0)) < 3.0
+
+
+# --------------------------------------------------------------------------
+# Diagnostics: Galilean invariance fixes how energy, momentum and angular
+# momentum change under a shift of origin and a boost.
+
+def pin_diagnostics_galilean_boost():
+    """A system with sum m x = 0 and sum m v = 0, shifted by C and boosted by
+    V: P = M V, L = L0 + M C x V, KE = KE0 + M |V|^2 / 2, PE unchanged."""
+    m, x, v = _random_system(60, 23)
+    M = m.sum()
+    x = x - (x @ m)[:, None] / M
+    v = v - (v @ m)[:, None] / M
+    eps = 0.02
+    d0 = oracle.diagnostics(m, x, v, eps)
+    C = np.array([0.75, -1.5, 0.25])
+    V = np.array([0.3, -0.2, 0.7])
+    d1 = oracle.diagnostics(m, x + C[:, None], v + V[:, None], eps)
+    assert _rel(d1["P"], M * V) < 1e-13
+    assert np.max(np.abs(d0["P"])) < 1e-15
+    assert _rel(d1["L"], d0["L"] + M * np.cross(C, V)) < 1e-13
+    assert abs(d1["KE"] - (d0["KE"] + 0.5 * M * V @ V)) < 1e-13 * d1["KE"]
+    assert abs(d1["PE"] - d0["PE"]) < 1e-13 * abs(d0["PE"])
+
+
+def pin_diagnostics_two_body_closed_form():
+    """Two bodies at x = -/+ (d/2) e_x with velocities -/+ (w/2) e_y:
+    L = 2 m (d/2)(w/2) e_z, P = 0, KE = m w^2 / 4, PE = -m^2 / sqrt(d^2+eps^2)."""
+    mm, d, w, eps = 0.5, 1.5, 0.8, 0.1
+    m = np.array([mm, mm])
+    x = np.array([[-d / 2, d / 2], [0.0, 0.0], [0.0, 0.0]])
+    v = np.array([[0.0, 0.0], [-w / 2, w / 2], [0.0, 0.0]])
+    dg = oracle.diagnostics(m, x, v, eps)
+    assert _rel(dg["L"], [0.0, 0.0, mm * d * w / 2]) < 1e-15
+    assert np.all(dg["P"] == 0.0)
+    assert abs(dg["KE"] - mm * w * w / 4) < 1e-16
+    assert abs(dg["PE"] + mm * mm / math.sqrt(d * d + eps * eps)) < 1e-15
+
+
+def pin_boosted_kepler_momentum():
+    """The e = 0.5 Kepler pair boosted by V: the block-step run keeps
+    P = M V and moves the centre of mass as X(t) = X(0) + V t."""
+    m, x, v = _kepler_state()
+    V = np.array([0.25, -0.5, 0.125])
+    v = v + V[:, None]
+    sim = oracle.Sim(m, x, v, eps=0.0)
+    d0 = sim.diagnostics()
+    assert _rel(d0["P"], V * m.sum()) < 1e-15
+    sim.run(1.0, max_steps=20000)
+    d1 = sim.diagnostics()
+    assert _rel(d1["P"], d0["P"]) < 1e-12
+    com = (sim.x @ m) / m.sum()
+    assert np.max(np.abs(com - V * 1.0)) < 1e-12
+
+
 def pin_j_slices_sum_to_total():
     """The paper's j-parallel partition: partial sums over contiguous j-slices,
     added in slice order, give the full sum up to FP64 rounding (Sect. 3)."""
@@ -396,6 +523,13 @@ ALL_PINS = [
     pin_gradient_of_potential_energy,
     pin_jerk_is_time_derivative,
     pin_active_subset_matches_full,
+    pin_force_abs_two_body,
+    pin_force_abs_rotating_ring,
+    pin_force_abs_collinear_equality,
+    pin_force_abs_bounds,
+    pin_diagnostics_galilean_boost,
+    pin_diagnostics_two_body_closed_form,
+    pin_boosted_kepler_momentum,
     pin_j_slices_sum_to_total,
     pin_predictor_exact_on_cubic,
     pin_corrector_exact_on_quintic,

@@ -35,6 +35,17 @@ MUTANTS = {
     "quantize_no_commensurability": ("dt_new >= 2.0 * dt_old && fmod(t_now, 2.0 * dt_old) == 0.0", "dt_new >= 2.0 * dt_old"),
     "quantize_free_growth": ("        dt_new = 2.0 * dt_old;\n    } else {", "        ;\n    } else {"),
     "slice_drop_last": ("if (e > n) e = n;", "if (e > n) e = n - 1;"),
+    "abs_drop_mass_factor": ("sa += mr3 * sqrt(dx * dx + dy * dy + dz * dz);", "sa += sqrt(dx * dx + dy * dy + dz * dz);"),
+    "abs_drop_radial_jerk": ("const double wx = dvx - c * dx,", "const double wx = dvx,"),
+    "abs_jerk_coeff": ("const double c = 3.0 * (dx * dvx + dy * dvy + dz * dvz) * rinv * rinv;",
+                       "const double c = 2.0 * (dx * dvx + dy * dvy + dz * dvz) * rinv * rinv;"),
+    "abs_pot_power": ("sp += m[j] * rinv;", "sp += m[j] * rinv * rinv;"),
+    "abs_self_term": ("        double sa = 0.0, sk = 0.0, sp = 0.0;\n        for (int64_t j = 0; j < n; ++j) {\n            if (j == i) continue;",
+                      "        double sa = 0.0, sk = 0.0, sp = 0.0;\n        for (int64_t j = 0; j < n; ++j) {"),
+    "diag_momentum_sign": ("p[d] += m[i] * vi[d];", "p[d] -= m[i] * vi[d];"),
+    "diag_momentum_index": ("p[d] += m[i] * vi[d];", "p[d] += m[i] * vi[0];"),
+    "diag_angmom_sign": ("l[2] += m[i] * (xi[0] * vi[1] - xi[1] * vi[0]);", "l[2] += m[i] * (xi[1] * vi[0] - xi[0] * vi[1]);"),
+    "diag_kinetic_half": ("ke += 0.5 * m[i] *", "ke += m[i] *"),
 }
 
 CHILD = r"""
