@@ -72,10 +72,12 @@ typedef enum {
 
 /* Arithmetic of the pairwise kernel.
  *   NBODY_FP64:  plain FP64 throughout.
- *   NBODY_MIXED: positions differenced in extended precision (FP64 or
- *                double-single), pair terms in FP32, partial sums over short
- *                j-windows in FP32 flushed into FP64 totals.  Predictor,
- *                corrector and time steps stay FP64 in both modes. */
+ *   NBODY_MIXED: positions held in FP64 and differenced with FP64
+ *                accuracy (tile-relative, FP64 or double-single, see
+ *                nbody_tuning), pair terms in FP32, partial sums over short
+ *                j-windows in FP32 flushed into FP64 totals, near pairs in
+ *                FP64.  Predictor, corrector and time steps stay FP64 in
+ *                both modes. */
 typedef enum { NBODY_FP64 = 0, NBODY_MIXED = 1 } nbody_precision;
 
 typedef struct {
@@ -127,8 +129,10 @@ NBODY_API nbody_status nbody_predict(nbody_ctx *ctx, const double *t_pred);
  * every predicted particle j != i of the same cluster.  The predicted state
  * is that of the last nbody_predict; after block steps (nbody_step), every
  * particle is first predicted again to its cluster's current time.
- *   active_idx: device, n_active global particle ids, cluster-major and
- *               ascending inside each cluster.
+ *   active_idx: device, n_active global particle ids, cluster-major, each
+ *               id at most once (any order inside a cluster; lists in the
+ *               storage order of nbody_get_layout run fastest in mixed
+ *               precision).
  *   active_offsets: device, n_clusters+1 int64; the entries of cluster c are
  *               active_idx[active_offsets[c] .. active_offsets[c+1]).
  *   acc, jerk: device, [3][n_active] FP64 outputs; pot: device [n_active]
@@ -187,7 +191,14 @@ NBODY_API nbody_status nbody_get_state(nbody_ctx *ctx, void *host_buf, size_t by
 NBODY_API nbody_status nbody_set_state(nbody_ctx *ctx, const void *host_buf, size_t bytes);
 
 /* Byte offsets, inside the workspace, of the FP64 state arrays, so the owner
- * of the workspace can read them in place (e.g. as tensors). */
+ * of the workspace can read them in place (e.g. as tensors).  The arrays are
+ * in the library's storage order, not in particle-id order: inside each
+ * cluster the library stores particles along a Morton curve of their
+ * initial positions (spatially close particles in consecutive slots, which
+ * the mixed force pass relies on).  Slot q of every array holds particle
+ * order[q]; entries of a cluster stay inside the cluster's id range.  An
+ * active list given in storage order (active_idx[q] = order[slot]) gives the
+ * fastest mixed force pass. */
 typedef struct {
     int64_t n_total;
     int32_t n_clusters;
@@ -195,6 +206,7 @@ typedef struct {
     size_t m, x, v, a, k, t, dt; /* [n], [3][n], [3][n], [3][n], [3][n], [n], [n] */
     size_t xp, vp;               /* predicted state, [3][n] each                 */
     size_t pot;                  /* potential of the last block (compute_pot)    */
+    size_t order;                /* int32 [n]: particle id stored at each slot   */
 } nbody_layout;
 NBODY_API nbody_status nbody_get_layout(const nbody_ctx *ctx, nbody_layout *out);
 
@@ -220,21 +232,39 @@ NBODY_API nbody_status nbody_get_layout(const nbody_ctx *ctx, nbody_layout *out)
  *              j-split layouts, at higher occupancy; results per layout
  *              are the same bits either way.
  *   grid: persistent workgroups of the force launch (default: 8 per CU).
- *   mixed_format: positions of the mixed kernel as double-single FP32
- *                 pairs (0) or FP64 (1, default); either way the difference
- *                 x_j - x_i is formed exactly enough and rounded to FP32.
+ *   mixed_format: how the mixed kernel forms the FP32 pair difference
+ *                 x_j - x_i: 0 from double-single FP32 pairs
+ *                 (hi_j - hi_i) + (lo_j - lo_i); 1 in FP64 from the FP64
+ *                 positions, rounded once; 2 (default) tile-relative: every
+ *                 position is rounded to FP32 relative to the centre of its
+ *                 LDS tile (kTile consecutive slots, compact in space), so
+ *                 the difference is one FP32 subtraction; pairs much closer
+ *                 than their tile's size are caught by the near test below.
  *   rsq_bias_correct: 1 (default) removes the mean relative error of the
  *                 hardware FP32 reciprocal square root, measured on the
  *                 device at nbody_init, from the mixed kernel's sums (each
  *                 FP32 window is scaled in FP64 by 1 - 3b, potential 1 - b);
  *                 0 leaves the hardware estimate as is.
- *   near_tau: in the mixed kernel no pair whose term m_j / R^2 exceeds
- *                 near_tau * |a_i| (|a_i| from the last step) is summed in
- *                 FP32: a window of 32 j that holds one is evaluated in
- *                 FP64 instead (default 0.25; 0 turns this off).  One FP32
- *                 term carries a few units of FP32 rounding, which limits
- *                 the relative force error only when that term is
- *                 comparable to the whole sum (close neighbours). */
+ *   near_tau, near_tau_k: in the mixed kernel no pair whose acceleration
+ *                 term m_j / R^2 may exceed near_tau * |a_i|, or whose
+ *                 jerk term (at most 2 m_j |v_j - v_i| / R^3) may exceed
+ *                 near_tau_k * |k_i| (|a_i|, |k_i| from the last step), is
+ *                 summed in FP32: a window of 32 j that may hold one is
+ *                 evaluated in FP64 instead (defaults 0.25 and 1;
+ *                 near_tau = 0 turns the whole test off, near_tau_k = 0 only
+ *                 its jerk part).  One FP32 term carries a few units of FP32
+ *                 rounding, which limits the relative error of a sum only
+ *                 when that term is comparable to the whole sum (close
+ *                 neighbours).
+ *   mid_tau: tile-relative format only.  Its FP32 coordinates carry an
+ *                 error of about 2^-24 times the tile's size, so a pair much
+ *                 closer than its tile is large loses precision in its
+ *                 difference although its term passes the test above: a
+ *                 window whose closest pair has term * (L / R) above
+ *                 mid_tau * |a_i| (or the jerk analogue above mid_tau * |k_i|)
+ *                 is summed again with FP64 position differences (L: the
+ *                 i's distance from the tile centre plus the tile's size;
+ *                 default 4). */
 typedef struct {
     int32_t target_items;
     int32_t min_block[4];
@@ -244,6 +274,8 @@ typedef struct {
     double near_tau;
     int32_t small_cluster_n;
     int32_t small_min_block[4];
+    double near_tau_k;
+    double mid_tau;
 } nbody_tuning;
 NBODY_API nbody_status nbody_get_tuning(const nbody_ctx *ctx, nbody_tuning *out);
 NBODY_API nbody_status nbody_set_tuning(nbody_ctx *ctx, const nbody_tuning *t);

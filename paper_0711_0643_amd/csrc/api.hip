@@ -11,6 +11,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 #include <utility>
 #include <vector>
@@ -24,10 +25,10 @@ using namespace nb;
 namespace {
 
 constexpr uint32_t kStateMagic = 0x5453424eu;  // "NBST"
-constexpr uint32_t kStateVersion = 1;
+constexpr uint32_t kStateVersion = 2;
 
 struct Layout {
-  size_t coff, eps, cid, ch_cluster, ch_begin, cl_ch;
+  size_t coff, eps, cid, ch_cluster, ch_begin, cl_ch, order, slot_of, tmeta, ulist;
   size_t m, x, v, a, k, t, dt, xp, vp, pot, jr;
   size_t tpred, tnow, inter, steps, cm2, acount, umin, act, aoff, plan, offs, ctl, part, fout, status, eout;
   size_t total;
@@ -54,6 +55,10 @@ Layout make_layout(int64_t n, int32_t nc) {
   L.ch_cluster = take(4 * (size_t)L.nch_max);
   L.ch_begin = take(8 * ((size_t)L.nch_max + 1));
   L.cl_ch = take(4 * (C + 1));
+  L.order = take(4 * N);
+  L.slot_of = take(4 * N);
+  L.tmeta = take(8 * kTileMeta * (size_t)L.nch_max);
+  L.ulist = take(4 * N);
   L.m = take(8 * N);
   L.x = take(24 * N);
   L.v = take(24 * N);
@@ -85,6 +90,54 @@ Layout make_layout(int64_t n, int32_t nc) {
   return L;
 }
 
+// Spread the low 21 bits of v to every third bit (Morton interleave).
+uint64_t spread3(uint64_t v) {
+  v &= 0x1fffffULL;
+  v = (v | v << 32) & 0x1f00000000ffffULL;
+  v = (v | v << 16) & 0x1f0000ff0000ffULL;
+  v = (v | v << 8) & 0x100f00f00f00f00fULL;
+  v = (v | v << 4) & 0x10c30c30c30c30c3ULL;
+  v = (v | v << 2) & 0x1249249249249249ULL;
+  return v;
+}
+
+// Storage order of the particles: inside each cluster, ascending Morton
+// code of the initial position in the cluster's bounding box (21 bits per
+// axis), ties by particle id, so that consecutive slots (and the kTile slots
+// of a force tile) are close in space.  order[slot] = particle id.
+std::vector<int32_t> morton_order(int64_t n, int32_t nc, const int64_t* coff, const double* x) {
+  std::vector<int32_t> order((size_t)n);
+  std::vector<std::pair<uint64_t, int32_t>> key;
+  for (int c = 0; c < nc; ++c) {
+    const int64_t b = coff[c], e = coff[c + 1];
+    double lo[3], hi[3];
+    for (int d = 0; d < 3; ++d) {
+      lo[d] = INFINITY;
+      hi[d] = -INFINITY;
+      for (int64_t i = b; i < e; ++i) {
+        lo[d] = fmin(lo[d], x[d * n + i]);
+        hi[d] = fmax(hi[d], x[d * n + i]);
+      }
+    }
+    double ext = 0.0;
+    for (int d = 0; d < 3; ++d) ext = fmax(ext, hi[d] - lo[d]);
+    const double scale = ext > 0.0 ? 2097151.0 / ext : 0.0;
+    key.resize((size_t)(e - b));
+    for (int64_t i = b; i < e; ++i) {
+      uint64_t code = 0;
+      for (int d = 0; d < 3; ++d) {
+        double q = (x[d * n + i] - lo[d]) * scale;
+        q = q < 0.0 ? 0.0 : q > 2097151.0 ? 2097151.0 : q;
+        code |= spread3((uint64_t)q) << d;
+      }
+      key[(size_t)(i - b)] = {code, (int32_t)i};
+    }
+    std::sort(key.begin(), key.end());
+    for (int64_t i = b; i < e; ++i) order[(size_t)i] = key[(size_t)(i - b)].second;
+  }
+  return order;
+}
+
 bool valid_params(const nbody_params* p) {
   if (!p) return false;
   if (!(p->eta > 0.0) || !isfinite(p->eta)) return false;
@@ -111,7 +164,7 @@ struct nbody_ctx {
   int32_t nch = 0;
   int grid = 2048;        // persistent force grid
   int target_items = 2048;  // work items a force pass aims at per cluster
-  int mixed_mode = kMX64; // position format of the mixed kernel
+  int mixed_mode = kTR;   // position format of the mixed kernel
   int rsq_correct = 1;    // remove the mean bias of v_rsq_f32 in the mixed kernel
   hipGraph_t graph[2] = {nullptr, nullptr};
   hipGraphExec_t gexec[2] = {nullptr, nullptr};  // one block step, of parity 0 and 1
@@ -129,6 +182,11 @@ struct nbody_ctx {
   // matches t, dt; cleared by every call that changes them outside the graph
   bool sel_valid = false;
   std::vector<int64_t> coff;
+  std::vector<int32_t> order;  // particle id stored at each slot
+  // every cluster keeps the self pair of the mixed kernel finite in FP32
+  // (eps^2 representable, largest m / eps^3 far from overflow): the lean
+  // tile-relative build may run
+  bool lean_ok = false;
   Ctl ctl{};
   bool profile = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_pending;  // recorded, not yet read
@@ -183,7 +241,7 @@ nbody_status force_all_internal(nbody_ctx* c, int mode) {
   const DevState& s = c->s;
   HIP_OK(launch_identity(s, c->stream));
   HIP_OK(launch_plan(s, s.aoff, s.n, c->target_items, c->stream));
-  HIP_OK(launch_force(s, mode, true, c->ctl.near_tau > 0.0, split_only(c), s.act, c->grid, -1, c->target_items,
+  HIP_OK(launch_force(s, mode, true, c->ctl.near_tau > 0.0, split_only(c), c->lean_ok, s.act, c->grid, -1, c->target_items,
                       c->stream));
   HIP_OK(launch_reduce(s, s.aoff, s.n, s.fout, s.fout + 3 * s.n, s.fout + 6 * s.n, c->stream));
   return NBODY_OK;
@@ -221,7 +279,8 @@ hipError_t capture_steps(nbody_ctx* c, int steps, int par0, hipGraph_t* g) {
     const int par = (par0 + k) & 1;
     e = launch_select(s, c->target_items, mode, par, c->cap_stream);
     if (e == hipSuccess)
-      e = launch_force(s, mode, c->p.compute_pot != 0, c->ctl.near_tau > 0.0, split_only(c), s.act, c->grid, par,
+      e = launch_force(s, mode, c->p.compute_pot != 0, c->ctl.near_tau > 0.0, split_only(c), c->lean_ok, s.act,
+                       c->grid, par,
                        c->target_items, c->cap_stream);
     if (e == hipSuccess) e = launch_reduce_correct_step(s, c->p.compute_pot != 0, par, c->target_items, c->cap_stream);
   }
@@ -262,9 +321,9 @@ struct Part {
 std::vector<Part> state_parts(const nbody_ctx* c) {
   const size_t N = (size_t)c->n, C = (size_t)c->nc;
   const Layout& L = c->L;
-  return {{L.coff, 8 * (C + 1)}, {L.eps, 8 * C}, {L.m, 8 * N},   {L.x, 24 * N},    {L.v, 24 * N},
-          {L.a, 24 * N},         {L.k, 24 * N},  {L.t, 8 * N},   {L.dt, 8 * N},    {L.tnow, 8 * C},
-          {L.inter, 8 * C},      {L.steps, 8 * C}};
+  return {{L.coff, 8 * (C + 1)}, {L.eps, 8 * C}, {L.order, 4 * N}, {L.slot_of, 4 * N}, {L.m, 8 * N},
+          {L.x, 24 * N},         {L.v, 24 * N},  {L.a, 24 * N},     {L.k, 24 * N},       {L.t, 8 * N},
+          {L.dt, 8 * N},         {L.tnow, 8 * C}, {L.inter, 8 * C}, {L.steps, 8 * C}};
 }
 }  // namespace
 
@@ -320,6 +379,28 @@ nbody_status nbody_init(nbody_ctx** out, int64_t n_total, int32_t n_clusters, co
   c->nc = n_clusters;
   c->coff.assign(cluster_offsets, cluster_offsets + n_clusters + 1);
 
+  c->lean_ok = true;
+  for (int cc = 0; cc < n_clusters; ++cc) {
+    double mmax = 0.0;
+    for (int64_t i = cluster_offsets[cc]; i < cluster_offsets[cc + 1]; ++i) mmax = fmax(mmax, m[i]);
+    const float e2 = (float)(eps[cc] * eps[cc]);
+    if (!(e2 >= 1e-30f) || !(mmax / (eps[cc] * eps[cc] * eps[cc]) < 1e30)) c->lean_ok = false;
+  }
+  // storage order: Morton order inside each cluster; the inputs are copied
+  // to the device in that order
+  c->order = morton_order(n_total, n_clusters, cluster_offsets, x);
+  std::vector<int32_t> slot_of((size_t)n_total);
+  std::vector<double> ms((size_t)n_total), xs(3 * (size_t)n_total), vs(3 * (size_t)n_total);
+  for (int64_t q = 0; q < n_total; ++q) {
+    const int64_t id = c->order[(size_t)q];
+    slot_of[(size_t)id] = (int32_t)q;
+    ms[(size_t)q] = m[id];
+    for (int d = 0; d < 3; ++d) {
+      xs[(size_t)(d * n_total + q)] = x[d * n_total + id];
+      vs[(size_t)(d * n_total + q)] = v[d * n_total + id];
+    }
+  }
+
   int dev = 0, cus = 256;
   if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   c->grid = cus * 8;
@@ -352,6 +433,10 @@ nbody_status nbody_init(nbody_ctx** out, int64_t n_total, int32_t n_clusters, co
   s.ch_cluster = (const int32_t*)(w + L.ch_cluster);
   s.ch_begin = (const int64_t*)(w + L.ch_begin);
   s.cl_ch = (const int32_t*)(w + L.cl_ch);
+  s.order = (int32_t*)(w + L.order);
+  s.slot_of = (int32_t*)(w + L.slot_of);
+  s.tmeta = (double*)(w + L.tmeta);
+  s.ulist = (int32_t*)(w + L.ulist);
   s.m = (double*)(w + L.m);
   s.x = (double*)(w + L.x);
   s.v = (double*)(w + L.v);
@@ -390,6 +475,8 @@ nbody_status nbody_init(nbody_ctx** out, int64_t n_total, int32_t n_clusters, co
   c->ctl.vmin_small[2] = 24;
   c->ctl.vmin_small[3] = 6;
   c->ctl.near_tau = 0.25;
+  c->ctl.near_tau_k = 1.0;
+  c->ctl.mid_tau = 4.0;
 
   const size_t N = (size_t)n_total;
   hipStream_t st = c->stream;
@@ -401,9 +488,11 @@ nbody_status nbody_init(nbody_ctx** out, int64_t n_total, int32_t n_clusters, co
   ok = ok && hipMemcpyAsync(w + L.ch_cluster, ch_cluster.data(), 4 * ch_cluster.size(), hipMemcpyHostToDevice, st) == hipSuccess;
   ok = ok && hipMemcpyAsync(w + L.ch_begin, ch_begin.data(), 8 * ch_begin.size(), hipMemcpyHostToDevice, st) == hipSuccess;
   ok = ok && hipMemcpyAsync(w + L.cl_ch, cl_ch.data(), 4 * cl_ch.size(), hipMemcpyHostToDevice, st) == hipSuccess;
-  ok = ok && hipMemcpyAsync(w + L.m, m, 8 * N, hipMemcpyHostToDevice, st) == hipSuccess;
-  ok = ok && hipMemcpyAsync(w + L.x, x, 24 * N, hipMemcpyHostToDevice, st) == hipSuccess;
-  ok = ok && hipMemcpyAsync(w + L.v, v, 24 * N, hipMemcpyHostToDevice, st) == hipSuccess;
+  ok = ok && hipMemcpyAsync(w + L.order, c->order.data(), 4 * N, hipMemcpyHostToDevice, st) == hipSuccess;
+  ok = ok && hipMemcpyAsync(w + L.slot_of, slot_of.data(), 4 * N, hipMemcpyHostToDevice, st) == hipSuccess;
+  ok = ok && hipMemcpyAsync(w + L.m, ms.data(), 8 * N, hipMemcpyHostToDevice, st) == hipSuccess;
+  ok = ok && hipMemcpyAsync(w + L.x, xs.data(), 24 * N, hipMemcpyHostToDevice, st) == hipSuccess;
+  ok = ok && hipMemcpyAsync(w + L.v, vs.data(), 24 * N, hipMemcpyHostToDevice, st) == hipSuccess;
   ok = ok && hipStreamSynchronize(st) == hipSuccess;
   if (!ok) {
     delete c;
@@ -471,6 +560,7 @@ nbody_status nbody_force(nbody_ctx* c, const int32_t* active_idx, const int64_t*
   const nbody_status r = complete_prediction(c);
   if (r != NBODY_OK) return r;
   c->sel_valid = false;  // the plan is replaced
+  HIP_OK(launch_map_active(s, active_idx, n_active, c->stream));  // particle ids -> slots
   HIP_OK(launch_plan(s, active_offsets, n_active, c->target_items, c->stream));
   std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
   if (c->profile) {
@@ -483,8 +573,8 @@ nbody_status nbody_force(nbody_ctx* c, const int32_t* active_idx, const int64_t*
     }
     HIP_OK(hipEventRecord(ev.first, c->stream));
   }
-  HIP_OK(launch_force(s, force_mode(c), pot != nullptr, c->ctl.near_tau > 0.0, split_only(c), active_idx, c->grid,
-                      -1, c->target_items, c->stream));
+  HIP_OK(launch_force(s, force_mode(c), pot != nullptr, c->ctl.near_tau > 0.0, split_only(c), c->lean_ok, s.ulist,
+                      c->grid, -1, c->target_items, c->stream));
   if (c->profile) {
     HIP_OK(hipEventRecord(ev.second, c->stream));
     c->prof_pending.push_back(ev);
@@ -502,7 +592,8 @@ nbody_status nbody_correct(nbody_ctx* c, const int32_t* active_idx, const int64_
   const nbody_status r = complete_prediction(c);
   if (r != NBODY_OK) return r;
   c->sel_valid = false;  // t and dt change
-  HIP_OK(launch_correct(c->s, active_idx, active_offsets, n_active, acc, jerk, c->stream));
+  HIP_OK(launch_map_active(c->s, active_idx, n_active, c->stream));  // particle ids -> slots
+  HIP_OK(launch_correct(c->s, c->s.ulist, active_offsets, n_active, acc, jerk, c->stream));
   return NBODY_OK;
 }
 
@@ -584,12 +675,13 @@ nbody_status nbody_progress(nbody_ctx* c, double* t_host, int64_t* steps_host, d
 }
 
 // State blob: header {magic, version, n (int64), nc (int32), pad} then
-// coff[nc+1] (int64), eps[nc], m[n], x[3n], v[3n], a[3n], k[3n], t[n], dt[n],
-// tnow[nc], inter[nc] (FP64), steps[nc] (int64).
+// coff[nc+1] (int64), eps[nc], order[n], slot_of[n] (int32: the storage
+// order), then in storage order m[n], x[3n], v[3n], a[3n], k[3n], t[n],
+// dt[n], and tnow[nc], inter[nc] (FP64), steps[nc] (int64).
 nbody_status nbody_state_bytes(const nbody_ctx* c, size_t* bytes) {
   if (!c || !bytes) return NBODY_E_INVAL;
   const size_t N = (size_t)c->n, C = (size_t)c->nc;
-  *bytes = 24 + 8 * (C + 1) + 8 * C + 8 * (15 * N) + 8 * 3 * C;
+  *bytes = 24 + 8 * (C + 1) + 8 * C + 8 * N + 8 * (15 * N) + 8 * 3 * C;
   return NBODY_OK;
 }
 
@@ -624,6 +716,20 @@ nbody_status nbody_set_state(nbody_ctx* c, const void* host_buf, size_t bytes) {
   memcpy(nc2, h + 16, 8);
   if (hdr[0] != kStateMagic || hdr[1] != kStateVersion || n != c->n || nc2[0] != c->nc) return NBODY_E_INVAL;
   if (memcmp(h + 24, c->coff.data(), 8 * ((size_t)c->nc + 1)) != 0) return NBODY_E_INVAL;
+  // the storage order of the blob: every slot holds a particle of its own
+  // cluster, and slot_of inverts order
+  const size_t N = (size_t)c->n;
+  std::vector<int32_t> order(N), slot_of(N);
+  const size_t oo = 24 + 8 * ((size_t)c->nc + 1) + 8 * (size_t)c->nc;
+  memcpy(order.data(), h + oo, 4 * N);
+  memcpy(slot_of.data(), h + oo + 4 * N, 4 * N);
+  for (int cc = 0; cc < c->nc; ++cc) {
+    for (int64_t q = c->coff[cc]; q < c->coff[cc + 1]; ++q) {
+      const int32_t id = order[(size_t)q];
+      if (id < c->coff[cc] || id >= c->coff[cc + 1] || slot_of[(size_t)id] != q) return NBODY_E_INVAL;
+    }
+  }
+  c->order = order;
   size_t o = 24;
   for (const Part& p : state_parts(c)) {
     HIP_OK(hipMemcpyAsync(c->ws + p.off, h + o, p.bytes, hipMemcpyHostToDevice, c->stream));
@@ -654,6 +760,7 @@ nbody_status nbody_get_layout(const nbody_ctx* c, nbody_layout* out) {
   out->xp = c->L.xp;
   out->vp = c->L.vp;
   out->pot = c->L.pot;
+  out->order = c->L.order;
   return NBODY_OK;
 }
 
@@ -664,9 +771,11 @@ nbody_status nbody_get_tuning(const nbody_ctx* c, nbody_tuning* t) {
   t->small_cluster_n = (int32_t)c->ctl.small_n;
   for (int i = 0; i < kNumVariants - 1; ++i) t->small_min_block[i] = c->ctl.vmin_small[i];
   t->grid = c->grid;
-  t->mixed_format = c->mixed_mode == kMX64 ? 1 : 0;
+  t->mixed_format = c->mixed_mode == kTR ? 2 : c->mixed_mode == kMX64 ? 1 : 0;
   t->rsq_bias_correct = c->rsq_correct;
   t->near_tau = c->ctl.near_tau;
+  t->near_tau_k = c->ctl.near_tau_k;
+  t->mid_tau = c->ctl.mid_tau;
   return NBODY_OK;
 }
 
@@ -674,9 +783,11 @@ nbody_status nbody_set_tuning(nbody_ctx* c, const nbody_tuning* t) {
   if (!c || !t) return NBODY_E_INVAL;
   if (t->target_items < 1 || t->target_items > kMaxTargetItems || t->grid < 1 || t->grid > (1 << 20))
     return NBODY_E_INVAL;
-  if (t->mixed_format != 0 && t->mixed_format != 1) return NBODY_E_INVAL;
+  if (t->mixed_format < 0 || t->mixed_format > 2) return NBODY_E_INVAL;
   if (t->rsq_bias_correct != 0 && t->rsq_bias_correct != 1) return NBODY_E_INVAL;
   if (!(t->near_tau >= 0.0) || !isfinite(t->near_tau)) return NBODY_E_INVAL;
+  if (!(t->near_tau_k >= 0.0) || !isfinite(t->near_tau_k)) return NBODY_E_INVAL;
+  if (!(t->mid_tau > 0.0) || !isfinite(t->mid_tau)) return NBODY_E_INVAL;
   for (int i = 0; i < kNumVariants - 1; ++i) {
     if (t->min_block[i] < 1 || t->small_min_block[i] < 1) return NBODY_E_INVAL;
     if (i > 0 && t->min_block[i - 1] < t->min_block[i]) return NBODY_E_INVAL;
@@ -685,10 +796,12 @@ nbody_status nbody_set_tuning(nbody_ctx* c, const nbody_tuning* t) {
   if (t->small_cluster_n < 0) return NBODY_E_INVAL;
   c->target_items = t->target_items;
   c->grid = t->grid;
-  c->mixed_mode = t->mixed_format == 1 ? kMX64 : kDS;
+  c->mixed_mode = t->mixed_format == 2 ? kTR : t->mixed_format == 1 ? kMX64 : kDS;
   const bool recal = c->rsq_correct != t->rsq_bias_correct;
   c->rsq_correct = t->rsq_bias_correct;
   c->ctl.near_tau = t->near_tau;
+  c->ctl.near_tau_k = t->near_tau_k;
+  c->ctl.mid_tau = t->mid_tau;
   for (int i = 0; i < kNumVariants - 1; ++i) c->ctl.vmin[i] = t->min_block[i];
   for (int i = 0; i < kNumVariants - 1; ++i) c->ctl.vmin_small[i] = t->small_min_block[i];
   c->ctl.small_n = t->small_cluster_n;

@@ -50,6 +50,15 @@ __host__ __device__ constexpr int variant_iwg(int v) { return kForceThreads / va
 // Mixed j-record in HBM: ten FP32 rows of n entries each.
 enum : int { JR_HX = 0, JR_HY, JR_HZ, JR_LX, JR_LY, JR_LZ, JR_VX, JR_VY, JR_VZ, JR_M, JR_ROWS };
 
+// Per-tile frame of the tile-relative mixed mode, one entry of kTileMeta
+// doubles per selection chunk (= LDS tile of kTile slots): the centre of the
+// bounding box of the predicted positions (origin of the FP32 relative
+// coordinates), the centre of the bounding box of the predicted velocities,
+// the half-diagonal of that velocity box (no velocity of the tile is farther
+// from the centre), the largest mass, and the half-diagonal of the position
+// box (no position of the tile is farther from the origin).
+enum : int { TM_OX = 0, TM_OY, TM_OZ, TM_VX, TM_VY, TM_VZ, TM_W, TM_MMAX, TM_D, kTileMeta };
+
 // Per-cluster force plan, written by the plan kernel.
 struct Plan {
   int64_t item_off;   // first work item of this cluster
@@ -79,8 +88,14 @@ struct Ctl {
   // the same for clusters of fewer than small_n particles
   int32_t vmin_small[kNumVariants - 1];
   int64_t small_n;
-  // mixed kernel: pairs with m_j / R^2 > near_tau |a_i| are done in FP64
+  // mixed kernel: pairs with m_j / R^2 > near_tau |a_i|, or whose jerk term
+  // may exceed near_tau_k |k_i|, are done in FP64
   double near_tau;
+  double near_tau_k;
+  // tile-relative mixed mode: a window whose closest pair has
+  // term * (L / R) above mid_tau |a_i| or |k_i| is summed again with FP64
+  // position differences (L: distance scale of the tile frame)
+  double mid_tau;
   // FP64 factors applied to the FP32 windows of the mixed kernel (bias of
   // the hardware reciprocal square root removed): R^-3 terms, R^-1 terms
   double rsq_scale3;
@@ -89,6 +104,11 @@ struct Ctl {
   int32_t pad3[2];
 };
 
+// Particles are stored in "slot" order: inside each cluster the library
+// sorts them along a Morton curve of their initial positions, so that the
+// kTile consecutive slots of an LDS tile are close in space.  The caller's
+// particle ids map to slots through slot_of; order maps back.  Every state
+// array of DevState is indexed by slot.
 struct DevState {
   int64_t n;          // particles, all clusters
   int32_t nc;         // clusters
@@ -99,6 +119,10 @@ struct DevState {
   const int32_t* ch_cluster;  // [nch] cluster of each selection chunk
   const int64_t* ch_begin;    // [nch+1] first particle of each chunk (ch_begin[nch] = n)
   const int32_t* cl_ch;       // [nc+1] first selection chunk of each cluster
+  int32_t* order;             // [n] particle id stored at each slot
+  int32_t* slot_of;           // [n] slot of each particle id
+  double* tmeta;              // [nch][kTileMeta] tile frames (tile-relative mixed mode)
+  int32_t* ulist;             // [n] a caller's active list mapped to slots
   double* m;
   double* x;
   double* v;

@@ -28,9 +28,30 @@
 //           (1 - 3b) for the R^-3 terms and (1 - b) for the potential.
 //   kMX64 : as kDS but the position difference is formed in FP64 from the
 //           predicted FP64 positions and rounded once to FP32.
+//   kTR   : tile-relative FP32 (layouts with one lane per i; the j-split
+//           layouts of small blocks form the position difference in FP64
+//           from the tile's FP64 copy instead).  Slots are sorted along a Morton curve, so
+//           the kTile j of a tile are close in space; the predictor records
+//           each tile's frame (bounding-box centres of the predicted
+//           positions and velocities).  The tile loader converts every j to
+//           FP32 coordinates relative to that frame (one FP64 subtraction
+//           per j and workgroup), each lane converts its i once per tile,
+//           and the pair difference is a single FP32 subtraction.  Its
+//           error, u (|x_i - o| + |x_j - o|), is that of a few ulps of the
+//           pair distance except for pairs much closer than the tile's
+//           size; those are the pairs the near test below sends to FP64.
 // The self pair (j == i) and the zero padding of a ragged last tile are
 // removed by zeroing 1/R, only on tiles where a lane's own i or the padding
 // can occur (a wave-uniform test), so full tiles run unmasked.
+//
+// Near pairs (mixed modes).  One FP32 pair term carries a few u = 2^-24 of
+// relative error, which limits the relative error of a sum only when the
+// term is small against the sum.  No pair stays in FP32 when its
+// acceleration term may exceed near_tau |a_i| or its jerk term may exceed
+// near_tau_k |k_i| (|a_i|, |k_i| from the last step).  A jerk term is at
+// most 2 m_j |v_j - v_i| / R^3 (the matrix I - 3 r r^T / R^2 has norm 2),
+// and |v_j - v_i| <= |v_i - v_c| + W for the tile's velocity centre v_c and
+// radius W.
 #include "common.h"
 #include "kernels.h"
 
@@ -46,22 +67,46 @@ struct alignas(16) RecMX {
   double x, y, z;
   float m, vx, vy, vz;
 };
+// kTR: FP32 position and velocity relative to the tile frame, FP32 mass.
+struct alignas(16) RecTR {
+  float x, y, z, m, vx, vy, vz, p0;
+};
+// kTR: the FP64 predicted state of a tile entry, for its near pairs.
+struct RecP64 {
+  double x, y, z, vx, vy, vz;
+};
+struct NoI64 {};
 
 template <int MODE> struct ModeT;
+// Rec: the LDS record of one j; I: what a lane keeps of one i for the pair
+// arithmetic; I64 (kTR): the i's FP64 predicted state, from which I is
+// formed anew for every tile.
 template <> struct ModeT<kF64> {
   using Rec = RecF64;
   struct I { double x, y, z, vx, vy, vz; };
+  using I64 = NoI64;
 };
 template <> struct ModeT<kDS> {
   using Rec = RecDS;
   struct I { float hx, hy, hz, lx, ly, lz, vx, vy, vz; };
+  using I64 = NoI64;
 };
 template <> struct ModeT<kMX64> {
   using Rec = RecMX;
   struct I { double x, y, z; float vx, vy, vz; };
+  using I64 = NoI64;
+};
+template <> struct ModeT<kTR> {
+  using Rec = RecTR;
+  struct I { float x, y, z, vx, vy, vz; };
+  using I64 = RecP64;
 };
 
-constexpr int kLdsBytes = kTile * 64;  // the largest record is 64 B
+// LDS per workgroup: one tile of records (at most 64 B each), or for kTR
+// the 32 B records followed by their 48 B FP64 copies.
+constexpr int kLdsBytes = kTile * 80;
+static_assert(kTile * (sizeof(RecTR) + sizeof(RecP64)) <= kLdsBytes, "kTR tile must fit");
+static_assert(kTile * sizeof(RecF64) <= kLdsBytes, "FP64 tile must fit");
 static_assert(kForceThreads * 7 * 8 <= kLdsBytes, "reduction buffer must fit the tile buffer");
 
 template <int MODE>
@@ -82,6 +127,7 @@ __device__ __forceinline__ typename ModeT<MODE>::Rec load_rec(const DevState& s,
     r.vx = jr[JR_VX * n + j]; r.vy = jr[JR_VY * n + j]; r.vz = jr[JR_VZ * n + j];
     r.p1 = 0.f;
   } else {
+    static_assert(MODE == kMX64, "kTR records are formed by the tile loader");
     const float* jr = s.jr;
     r.x = s.xp[j]; r.y = s.xp[n + j]; r.z = s.xp[2 * n + j];
     r.m = jr[JR_M * n + j];
@@ -109,12 +155,22 @@ __device__ __forceinline__ typename ModeT<MODE>::I load_i(const DevState& s, int
     d.hx = jr[JR_HX * n + i]; d.hy = jr[JR_HY * n + i]; d.hz = jr[JR_HZ * n + i];
     d.lx = jr[JR_LX * n + i]; d.ly = jr[JR_LY * n + i]; d.lz = jr[JR_LZ * n + i];
     d.vx = jr[JR_VX * n + i]; d.vy = jr[JR_VY * n + i]; d.vz = jr[JR_VZ * n + i];
-  } else {
+  } else if constexpr (MODE == kMX64) {
     const float* jr = s.jr;
     d.x = s.xp[i]; d.y = s.xp[n + i]; d.z = s.xp[2 * n + i];
     d.vx = jr[JR_VX * n + i]; d.vy = jr[JR_VY * n + i]; d.vz = jr[JR_VZ * n + i];
+  } else {
+    d.x = d.y = d.z = d.vx = d.vy = d.vz = 0.f;  // formed per tile from the FP64 state
   }
   return d;
+}
+
+__device__ __forceinline__ RecP64 load_p64(const DevState& s, int64_t i) {
+  const int64_t n = s.n;
+  RecP64 r;
+  r.x = s.xp[i]; r.y = s.xp[n + i]; r.z = s.xp[2 * n + i];
+  r.vx = s.vp[i]; r.vy = s.vp[n + i]; r.vz = s.vp[2 * n + i];
+  return r;
 }
 
 // 1/sqrt(r2) in FP64: hardware estimate, then y <- y + y e (1/2 + 3e/8) with
@@ -164,6 +220,10 @@ __device__ __forceinline__ Diff32 diff32(const typename ModeT<MODE>::I& I, const
     d.dx = (J.hx - I.hx) + (J.lx - I.lx);
     d.dy = (J.hy - I.hy) + (J.ly - I.ly);
     d.dz = (J.hz - I.hz) + (J.lz - I.lz);
+  } else if constexpr (MODE == kTR) {
+    d.dx = J.x - I.x;
+    d.dy = J.y - I.y;
+    d.dz = J.z - I.z;
   } else {
     d.dx = (float)(J.x - I.x);
     d.dy = (float)(J.y - I.y);
@@ -176,31 +236,58 @@ __device__ __forceinline__ Diff32 diff32(const typename ModeT<MODE>::I& I, const
   return d;
 }
 
+// kTR in the layouts that split j over lanes (small blocks, often small
+// clusters, where a tile spans much of the cluster): the position
+// difference is formed in FP64 from the tile's FP64 copy and the i's FP64
+// position and rounded once; velocities stay tile-relative FP32.
+__device__ __forceinline__ Diff32 diff32_tr64(const RecTR& J, const RecP64& Jp, const ModeT<kTR>::I& I,
+                                              const double* xi, float eps2f) {
+  Diff32 d;
+  d.dx = (float)(Jp.x - xi[0]);
+  d.dy = (float)(Jp.y - xi[1]);
+  d.dz = (float)(Jp.z - xi[2]);
+  d.dvx = J.vx - I.vx;
+  d.dvy = J.vy - I.vy;
+  d.dvz = J.vz - I.vz;
+  d.r2 = __builtin_fmaf(d.dz, d.dz, __builtin_fmaf(d.dy, d.dy, __builtin_fmaf(d.dx, d.dx, eps2f)));
+  return d;
+}
+
 // Weight of an FP32 pair in the per-pair near scheme: 1 when its term
-// m_j / R^2 (= t) is below the per-i threshold g, 0 above it (the pair then
-// goes to FP64).  Branch-free: (g - t) * 2^40 clamped to [0, 1], one FMA
-// from gB = g * 2^40 and a clamp, so the first pass and the FP64 re-scan get
-// the same weight bit for bit; the re-scan adds (1 - weight) of the pair in
-// FP64, so the split is exact even in the (measure-zero) fractional case.
+// (t = m_j / R^2 for the acceleration, m_j / R^3 for the jerk) is below the
+// per-i threshold g, 0 above it (the pair then goes to FP64).  Branch-free:
+// (g - t) * 2^40 clamped to [0, 1], one FMA from gB = g * 2^40 and a clamp,
+// so the first pass and the FP64 re-scan get the same weight bit for bit;
+// the re-scan adds (1 - weight) of the pair in FP64, so the split is exact
+// even in the (measure-zero) fractional case.
 constexpr float kNearScale = 1099511627776.0f;  // 2^40
+
 __device__ __forceinline__ float near_weight(float t, float gB) {
   return __builtin_amdgcn_fmed3f(__builtin_fmaf(-t, kNearScale, gB), 0.f, 1.f);
+}
+
+// Near weight of a pair from its m_j / R^2 (t) and m_j / R^3 (t3): the
+// acceleration threshold gB and the jerk threshold gkB (both times 2^40).
+__device__ __forceinline__ float near_weight2(float t, float t3, float gB, float gkB) {
+  return fminf(near_weight(t, gB), near_weight(t3, gkB));
 }
 
 // The rest of an FP32 pair, accumulated into the FP32 window.  ZERO: drop
 // the pair when `drop` is set.  WEIGHT: scale it by its near weight and keep
 // the smallest weight of the window in *wmin.
 template <bool ZERO, bool POT, bool WEIGHT>
-__device__ __forceinline__ void finish_f32(const Diff32& d, float m, bool drop, float gB, float* wmin, Acc32& A) {
+__device__ __forceinline__ void finish_f32(const Diff32& d, float m, bool drop, float gB, float gkB, float* wmin,
+                                           Acc32& A) {
   float rinv = __builtin_amdgcn_rsqf(d.r2);
   if (ZERO) rinv = drop ? 0.f : rinv;
   const float rinv2 = rinv * rinv;
   float mr, mr3;
   if (WEIGHT) {
     const float t = m * rinv2;  // m_j / R^2
-    const float w = near_weight(t, gB);
+    const float t3 = t * rinv;  // m_j / R^3
+    const float w = near_weight2(t, t3, gB, gkB);
     *wmin = fminf(*wmin, w);
-    mr3 = (t * w) * rinv;
+    mr3 = t3 * w;
     mr = POT ? m * rinv * w : 0.f;
   } else {
     mr = m * rinv;
@@ -219,9 +306,10 @@ __device__ __forceinline__ void finish_f32(const Diff32& d, float m, bool drop, 
 
 // Near weight of a pair recomputed for the FP64 re-scan, with exactly the
 // operations of the first pass.
-__device__ __forceinline__ float near_weight_again(const Diff32& d, float m, float gB) {
+__device__ __forceinline__ float near_weight_again(const Diff32& d, float m, float gB, float gkB) {
   const float rinv = __builtin_amdgcn_rsqf(d.r2);
-  return near_weight(m * (rinv * rinv), gB);
+  const float t = m * (rinv * rinv);
+  return near_weight2(t, t * rinv, gB, gkB);
 }
 
 // A pair of a mixed mode evaluated in FP64 from the same record: the
@@ -259,6 +347,29 @@ __device__ __forceinline__ void pair_mixed64(const typename ModeT<MODE>::I& I, c
   if (POT) A.v[6] -= mr;
 }
 
+// A kTR pair in FP64 from the FP64 predicted states (the mass is the
+// record's FP32 value widened), added straight into the FP64 totals.
+template <bool POT>
+__device__ __forceinline__ void pair_tr64(const RecP64& Fi, const RecP64& Fj, float m, double eps2, double share,
+                                          Acc64& A) {
+  const double dx = Fj.x - Fi.x, dy = Fj.y - Fi.y, dz = Fj.z - Fi.z;
+  const double dvx = Fj.vx - Fi.vx, dvy = Fj.vy - Fi.vy, dvz = Fj.vz - Fi.vz;
+  const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, __builtin_fma(dx, dx, eps2)));
+  const double rinv = rsqrt_f64(r2);
+  const double rinv2 = rinv * rinv;
+  const double mr = share * (double)m * rinv;
+  const double mr3 = mr * rinv2;
+  const double rv = __builtin_fma(dz, dvz, __builtin_fma(dy, dvy, dx * dvx));
+  const double al = (-3.0 * rinv2) * rv;
+  A.v[0] = __builtin_fma(mr3, dx, A.v[0]);
+  A.v[1] = __builtin_fma(mr3, dy, A.v[1]);
+  A.v[2] = __builtin_fma(mr3, dz, A.v[2]);
+  A.v[3] = __builtin_fma(mr3, __builtin_fma(al, dx, dvx), A.v[3]);
+  A.v[4] = __builtin_fma(mr3, __builtin_fma(al, dy, dvy), A.v[4]);
+  A.v[5] = __builtin_fma(mr3, __builtin_fma(al, dz, dvz), A.v[5]);
+  if (POT) A.v[6] -= mr;
+}
+
 // FP64 pass over the near windows of one tile, after the FP32 sweep (the
 // tile is still in LDS).  Bit p * NW + k of `flags` marks window k (F
 // entries from jl0 + k F) of i-particle p.  WIN (window test): the window's
@@ -267,40 +378,98 @@ __device__ __forceinline__ void pair_mixed64(const typename ModeT<MODE>::I& I, c
 // near weight w is below 1 adds (1 - w) of its FP64 value; w is recomputed
 // with exactly the operations of the FP32 pass.  Each lane walks its own
 // windows in ascending order, so the sums do not depend on the other lanes.
-// Kept inline and rolled: at this point the FP32 window state is dead, so
-// the FP64 temporaries fit beside the totals without spilling, and no call
-// (with its register saves in scratch memory) is needed.
+// Kept inline (no call, whose register saves would go through scratch
+// memory) and unrolled by 4 so that the LDS reads of consecutive pairs
+// overlap: at this point the FP32 window state is dead, so the FP64
+// temporaries fit beside the totals.
 template <int MODE, int F, int NW, int IPT, bool POT, bool WIN>
-__device__ __forceinline__ void near_windows_f64(const typename ModeT<MODE>::Rec* tile, int jl0, int64_t tile_j0,
-                                                 int64_t j_end, const int64_t* i_glob,
-                                                 const typename ModeT<MODE>::I* I, const float* gB, double eps2d,
-                                                 float eps2f, uint32_t flags, Acc64* A) {
+__device__ __forceinline__ void near_windows_f64(const DevState& s, const typename ModeT<MODE>::Rec* tile,
+                                                 const RecP64* tile64, int jl0, const int* own, int jend,
+                                                 const int64_t* i_glob, const typename ModeT<MODE>::I* I,
+                                                 const float* gB, const float* gkB, double eps2d, float eps2f,
+                                                 uint32_t flags, Acc64* A) {
 #pragma unroll
   for (int p = 0; p < IPT; ++p) {
     uint32_t f = (flags >> (p * NW)) & ((1u << NW) - 1u);
+    RecP64 Fi{0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if constexpr (MODE == kTR) {
+      if (f) Fi = load_p64(s, i_glob[p]);  // the i's FP64 state (rarely needed: not kept in registers)
+    }
     while (f) {
       const int jw = jl0 + __builtin_ctz(f) * F;
       f &= f - 1u;
-#pragma unroll 1
+#pragma unroll 4
       for (int u = 0; u < F; ++u) {
         const int jl = jw + u;
-        const int64_t jg = tile_j0 + jl;
-        if (jg == i_glob[p] || jg >= j_end) continue;
+        if (jl == own[p] || jl >= jend) continue;
         const typename ModeT<MODE>::Rec J = tile[jl];
-        if constexpr (WIN) {
-          pair_mixed64<MODE, POT>(I[p], J, eps2d, 1.0, A[p]);
-        } else {
-          const float wt = near_weight_again(diff32<MODE>(I[p], J, eps2f), J.m, gB[p]);
-          if (wt < 1.f) pair_mixed64<MODE, POT>(I[p], J, eps2d, 1.0 - (double)wt, A[p]);
+        double share = 1.0;
+        if constexpr (!WIN) {
+          Diff32 D;
+          if constexpr (MODE == kTR)
+            D = diff32_tr64(J, tile64[jl], I[p], &Fi.x, eps2f);
+          else
+            D = diff32<MODE>(I[p], J, eps2f);
+          const float wt = near_weight_again(D, J.m, gB[p], gkB[p]);
+          if (!(wt < 1.f)) continue;
+          share = 1.0 - (double)wt;
         }
+        if constexpr (MODE == kTR)
+          pair_tr64<POT>(Fi, tile64[jl], J.m, eps2d, share, A[p]);
+        else
+          pair_mixed64<MODE, POT>(I[p], J, eps2d, share, A[p]);
       }
+    }
+  }
+}
+
+// kTR with the window test: a window flagged "mid" may hold a pair much
+// closer than its tile is large.  Tile-relative FP32 coordinates carry an
+// error of about u (|x_i - o| + |x_j - o|), so for such a pair they lose
+// too much of the pair distance although its term is too small for the
+// near test.  The window is summed again in FP32 with the position
+// difference formed in FP64 (the tile's FP64 copy and the i's FP64
+// position, rounded once) and flushed with the same bias factors; its
+// first FP32 sum was left out.  Each lane walks its own windows in order.
+template <int F, int NW, int IPT, bool POT>
+__device__ __forceinline__ void mid_windows(const DevState& s, const RecTR* tile, const RecP64* tile64, int jl0,
+                                            const int* own, int jend, const int64_t* i_glob,
+                                            const ModeT<kTR>::I* I, float eps2f, double ca, double cp,
+                                            uint32_t mflags, Acc64* A) {
+#pragma unroll
+  for (int p = 0; p < IPT; ++p) {
+    uint32_t f = (mflags >> (p * NW)) & ((1u << NW) - 1u);
+    double xi[3] = {0.0, 0.0, 0.0};
+    if (f) {
+      const int64_t n = s.n, i = i_glob[p];
+      xi[0] = s.xp[i];
+      xi[1] = s.xp[n + i];
+      xi[2] = s.xp[2 * n + i];
+    }
+    while (f) {
+      const int jw = jl0 + __builtin_ctz(f) * F;
+      f &= f - 1u;
+      Acc32 B;
+#pragma unroll
+      for (int d = 0; d < 7; ++d) B.v[d] = 0.f;
+      float wdummy = 1.f;
+#pragma unroll 8
+      for (int u = 0; u < F; ++u) {
+        const int jl = jw + u;
+        const bool drop = jl == own[p] || jl >= jend;
+        const RecTR J = tile[jl];
+        finish_f32<true, POT, false>(diff32_tr64(J, tile64[jl], I[p], xi, eps2f), J.m, drop, 0.f, 0.f, &wdummy, B);
+      }
+#pragma unroll
+      for (int d = 0; d < 6; ++d) A[p].v[d] = __builtin_fma((double)B.v[d], ca, A[p].v[d]);
+      if (POT) A[p].v[6] = __builtin_fma((double)B.v[6], cp, A[p].v[6]);
     }
   }
 }
 
 // Sweep this lane's share of one LDS tile for its IPT i-particles.  jl0:
 // first tile-local j of the lane; PER: j per lane per tile; the global index
-// of tile entry u is tile_j0 + u.  Each j-record is read from LDS once and
+// of tile entry u is the tile start + u.  Each j-record is read from LDS once and
 // used for all IPT particles.  MASK drops the particle's own j and entries at
 // or past j_end.
 //
@@ -319,20 +488,26 @@ __device__ __forceinline__ void near_windows_f64(const typename ModeT<MODE>::Rec
 //    0 or 1 in the FP32 window, and the weight-0 pairs are added in FP64.
 // The FP64 work runs after the tile's FP32 sweep (near_windows_f64), in a
 // wave-uniform branch taken only when some lane marked a window.
-template <int MODE, int PER, int IPT, bool MASK, bool POT, bool NEAR>
-__device__ __forceinline__ void sweep_tile(const typename ModeT<MODE>::Rec* tile, const float* wmax, int jl0,
-                                           int64_t tile_j0, int64_t j_end, const int64_t* i_glob,
-                                           const typename ModeT<MODE>::I* I, const float* g, const float* gB,
-                                           double eps2d, float eps2f, double ca, double cp, Acc64* A) {
+// Near thresholds per i: with the window test (one lane per i) gsel = g =
+// near_tau |a_i| and ksel = the R^2 below which a window may hold a jerk
+// term above near_tau_k |k_i|; with per-pair weights gsel = g * 2^40 and
+// ksel = (near_tau_k |k_i| / (2 v)) * 2^40, the m_j / R^3 above which a
+// jerk term may exceed it (v bounds |v_j - v_i| over the tile).
+template <int MODE, int PER, int IPT, bool MASK, bool POT, bool NEAR, bool LEANW = false>
+__device__ __forceinline__ void sweep_tile(const DevState& s, const typename ModeT<MODE>::Rec* tile,
+                                           const RecP64* tile64, const float* wmax, int jl0, const int* own,
+                                           int jend, const int64_t* i_glob, const typename ModeT<MODE>::I* I,
+                                           const double (*xi64)[3], const float* gsel, const float* ksel,
+                                           const float* mthr, double eps2d, float eps2f, double ca, double cp,
+                                           Acc64* A) {
   if constexpr (MODE == kF64) {
 #pragma unroll 8
     for (int u = 0; u < PER; ++u) {
       const int jl = jl0 + u;
-      const int64_t jg = tile_j0 + jl;
       const RecF64 J = tile[jl];
 #pragma unroll
       for (int p = 0; p < IPT; ++p) {
-        const bool drop = MASK && (jg == i_glob[p] || jg >= j_end);
+        const bool drop = MASK && (jl == own[p] || jl >= jend);
         pair_f64<MASK, POT>(I[p], J, eps2d, drop, A[p]);
       }
     }
@@ -341,8 +516,11 @@ __device__ __forceinline__ void sweep_tile(const typename ModeT<MODE>::Rec* tile
     constexpr bool WGT = NEAR && !WIN;          // per-pair weights
     constexpr int F = PER < 32 ? PER : 32;      // FP32 window, then flush to FP64
     constexpr int NW = PER / F;                 // windows per tile
-    static_assert(IPT * NW <= 32, "near flags must fit 32 bits");
-    uint32_t flags = 0;  // near windows of this tile: bit p * NW + window
+    constexpr bool MID = WIN && MODE == kTR;    // mid windows (kTR, window test)
+    static_assert(IPT * NW <= (MID ? 16 : 32), "near flags must fit 32 bits");
+    // near windows of this tile: bit p * NW + window; mid windows: the same
+    // bits shifted by 16
+    uint32_t flags = 0;
     for (int w = 0; w < PER; w += F) {
       Acc32 B[IPT];
       float r2min[IPT];
@@ -353,17 +531,22 @@ __device__ __forceinline__ void sweep_tile(const typename ModeT<MODE>::Rec* tile
 #pragma unroll
         for (int d = 0; d < 7; ++d) B[p].v[d] = 0.f;
       }
-#pragma unroll
+      // per-pair weights carry more temporaries per pair: a partial unroll
+      // keeps the j-split layouts within their register budget
+#pragma unroll(WGT ? 8 : F)
       for (int u = 0; u < F; ++u) {
         const int jl = jl0 + w + u;
-        const int64_t jg = tile_j0 + jl;
         const typename ModeT<MODE>::Rec J = tile[jl];
 #pragma unroll
         for (int p = 0; p < IPT; ++p) {
-          const Diff32 D = diff32<MODE>(I[p], J, eps2f);
-          const bool drop = MASK && (jg == i_glob[p] || jg >= j_end);
+          Diff32 D;
+          if constexpr (MODE == kTR && PER != kTile)
+            D = diff32_tr64(J, tile64[jl], I[p], xi64[p], eps2f);
+          else
+            D = diff32<MODE>(I[p], J, eps2f);
+          const bool drop = MASK && (jl == own[p] || jl >= jend);
           if (WIN) r2min[p] = __builtin_fminf(r2min[p], (MASK && drop) ? INFINITY : D.r2);
-          finish_f32<MASK, POT, WGT>(D, J.m, drop, gB[p], &wmin, B[p]);
+          finish_f32<MASK, POT, WGT>(D, J.m, drop, gsel[p], ksel[p], &wmin, B[p]);
         }
       }
       // flush: the FP32 window times the factor that removes the mean bias
@@ -374,10 +557,19 @@ __device__ __forceinline__ void sweep_tile(const typename ModeT<MODE>::Rec* tile
       for (int p = 0; p < IPT; ++p) {
         double fa = ca, fp = cp;
         if constexpr (WIN) {
-          const bool cand = wmax[(jl0 + w) >> 5] > g[p] * r2min[p];
+          bool cand = (wmax[(jl0 + w) >> 5] > gsel[p] * r2min[p]) || (r2min[p] < ksel[p]);
+          // lean sweep (no masked variant): the window holding the i's own
+          // entry is always summed again in FP64, which skips that entry
+          if constexpr (LEANW) cand = cand || (unsigned)(own[p] - (jl0 + w)) < (unsigned)F;
           flags |= (uint32_t)cand << (p * NW + w / F);
-          fa = cand ? 0.0 : ca;
-          fp = cand ? 0.0 : cp;
+          bool redo = cand;
+          if constexpr (MID) {
+            const bool mid = !cand && r2min[p] < mthr[p];
+            flags |= (uint32_t)mid << (16 + p * NW + w / F);
+            redo = cand || mid;
+          }
+          fa = redo ? 0.0 : ca;
+          fp = redo ? 0.0 : cp;
         }
         if constexpr (WGT) flags |= (uint32_t)(wmin < 1.f) << (p * NW + w / F);
 #pragma unroll
@@ -386,9 +578,12 @@ __device__ __forceinline__ void sweep_tile(const typename ModeT<MODE>::Rec* tile
       }
     }
     if constexpr (NEAR) {
-      if (__any(flags != 0u))
-        near_windows_f64<MODE, F, NW, IPT, POT, WIN>(tile, jl0, tile_j0, j_end, i_glob, I, gB, eps2d, eps2f, flags,
-                                                     A);
+      if (__any(flags != 0u)) {
+        near_windows_f64<MODE, F, NW, IPT, POT, WIN>(s, tile, tile64, jl0, own, jend, i_glob, I, gsel, ksel, eps2d,
+                                                     eps2f, flags & 0xffffu, A);
+        if constexpr (MID)
+          mid_windows<F, NW, IPT, POT>(s, tile, tile64, jl0, own, jend, i_glob, I, eps2f, ca, cp, flags >> 16, A);
+      }
     }
   }
 }
@@ -407,16 +602,27 @@ __device__ __forceinline__ int find_cluster(const Plan* plan, int nc, int64_t it
 // One work item.  Layout: JL lanes per i-slot, IPT i-particles per lane
 // (IPT > 1 only with JL = 1); the chunk holds IWG = IPT * 256 / JL entries of
 // the cluster's active list.
-template <int MODE, int JL, int IPT, bool POT, bool NEAR>
+// LEAN (kTR with the near test, every softening large enough that the self
+// pair stays finite in FP32): the one-lane-per-i layouts have no masked
+// sweep.  The self pair has a zero position and velocity difference, so it
+// adds exactly nothing to a and k, and its window is always redone in FP64
+// (which skips it); padding records sit at 1e15, where every term is zero.
+// Without the masked copy of the sweep the kernel needs far fewer registers.
+template <int MODE, int JL, int IPT, bool POT, bool NEAR, bool LEAN = false>
 __device__ void run_item(const DevState& s, const int32_t* __restrict__ act, const Plan& P, int c,
                          int64_t local_item, unsigned char* lds, float* wmax) {
   static_assert(JL == 1 || IPT == 1, "several i per lane only with one lane per i");
   constexpr int SLOTS = kForceThreads / JL;  // i-slots per pass
   constexpr int IWG = SLOTS * IPT;
   constexpr int PER = kTile / JL;
+  constexpr bool FRAME = MODE == kTR || (NEAR && MODE != kF64);  // reads the tile frames
+  constexpr bool LEANW = LEAN && JL == 1 && NEAR && MODE == kTR;
+  constexpr float kPad = LEANW ? 1e15f : 0.f;  // position of padding records
   using Rec = typename ModeT<MODE>::Rec;
   using IT = typename ModeT<MODE>::I;
+  constexpr bool WIN = NEAR && PER == kTile;  // window test (else per-pair weights)
   Rec* tile = reinterpret_cast<Rec*>(lds);
+  RecP64* tile64 = reinterpret_cast<RecP64*>(lds + kTile * sizeof(RecTR));  // kTR only
 
   int tid = threadIdx.x;
   asm volatile("" : "+v"(tid));  // opaque here: nothing derived from it is hoisted out of the item loop
@@ -453,19 +659,25 @@ __device__ void run_item(const DevState& s, const int32_t* __restrict__ act, con
   const double eps2d = eps * eps;
   const float eps2f = (float)eps2d;
   const double ca = s.ctl->rsq_scale3, cp = s.ctl->rsq_scale1;
-  // near-pair threshold g = tau |a_i| (|a_i| of the last step), and g * 2^40
-  // for the per-pair weights; no threshold (infinity) while |a_i| is unknown
-  float g[IPT], gB[IPT];
+  // near-pair thresholds from the last step: g = tau |a_i| (times 2^40 for
+  // the per-pair weights), gk = tau_k |k_i|; infinity (no test) while
+  // unknown or zero
+  float gsel[IPT], gk[IPT];
+  const float tau_a = (float)s.ctl->near_tau, tau_k = (float)s.ctl->near_tau_k, tau_m = (float)s.ctl->mid_tau;
 #pragma unroll
   for (int p = 0; p < IPT; ++p) {
-    g[p] = INFINITY;
+    gsel[p] = INFINITY;
+    gk[p] = INFINITY;
     if (NEAR) {
       const int64_t n = s.n, i = i_glob[p];
       const double ax = s.a[i], ay = s.a[n + i], az = s.a[2 * n + i];
       const double gi = s.ctl->near_tau * sqrt(ax * ax + ay * ay + az * az);
-      if (gi > 0.0 && gi < 1e30) g[p] = (float)gi;
+      if (gi > 0.0 && gi < 1e30) gsel[p] = (float)gi;
+      const double kx = s.k[i], ky = s.k[n + i], kz = s.k[2 * n + i];
+      const double gki = s.ctl->near_tau_k * sqrt(kx * kx + ky * ky + kz * kz);
+      if (gki > 0.0 && gki < 1e30) gk[p] = (float)gki;
+      if (!WIN) gsel[p] = gsel[p] * kNearScale;
     }
-    gB[p] = g[p] * kNearScale;
   }
 
   const int64_t j_begin = c_begin + (int64_t)slice * P.slice_len;
@@ -473,30 +685,133 @@ __device__ void run_item(const DevState& s, const int32_t* __restrict__ act, con
   if (j_end > c_end) j_end = c_end;
 
   for (int64_t j0 = j_begin; j0 < j_end; j0 += kTile) {
+    // frame of this tile (selection chunk), the same for every thread
+    double fo[3] = {0.0, 0.0, 0.0}, fv[3] = {0.0, 0.0, 0.0};
+    float f_w = 0.f, f_mmax = 0.f, f_d = 0.f;
+    if constexpr (FRAME) {
+      const double* f = s.tmeta + (int64_t)(s.cl_ch[c] + (int)((j0 - c_begin) / kTile)) * kTileMeta;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        fo[d] = f[TM_OX + d];
+        fv[d] = f[TM_VX + d];
+      }
+      f_w = (float)f[TM_W];
+      f_mmax = (float)f[TM_MMAX];
+      f_d = (float)f[TM_D];
+    }
     __syncthreads();  // previous tile fully consumed
     static_assert(kTile == kForceThreads, "one record per thread");
     {
       const int64_t j = j0 + tid;
-      const Rec rec = (j < j_end) ? load_rec<MODE>(s, j) : zero_rec<MODE>();
-      tile[tid] = rec;
+      float mrec;
+      if constexpr (MODE == kTR) {
+        RecTR r = zero_rec<kTR>();
+        r.x = r.y = r.z = kPad;
+        RecP64 q{(double)kPad, (double)kPad, (double)kPad, 0.0, 0.0, 0.0};
+        if (j < j_end) {
+          q = load_p64(s, j);
+          r.x = (float)(q.x - fo[0]);
+          r.y = (float)(q.y - fo[1]);
+          r.z = (float)(q.z - fo[2]);
+          r.vx = (float)(q.vx - fv[0]);
+          r.vy = (float)(q.vy - fv[1]);
+          r.vz = (float)(q.vz - fv[2]);
+          r.m = s.jr[JR_M * s.n + j];
+        }
+        tile[tid] = r;
+        tile64[tid] = q;
+        mrec = r.m;
+      } else {
+        const Rec rec = (j < j_end) ? load_rec<MODE>(s, j) : zero_rec<MODE>();
+        tile[tid] = rec;
+        mrec = (float)rec.m;
+      }
       if (NEAR && JL == 1) {  // largest mass of each group of 32 entries (padding has m = 0)
-        float mm = (float)rec.m;
+        float mm = mrec;
 #pragma unroll
         for (int o = 16; o >= 1; o >>= 1) mm = fmaxf(mm, __shfl_xor(mm, o, 32));
         if ((tid & 31) == 0) wmax[tid >> 5] = mm;
       }
     }
+    // per i and tile: kTR coordinates relative to the frame (from the FP64
+    // state, reloaded rather than kept), and the jerk threshold (a jerk term
+    // is at most 2 m_j (|v_i - v_c| + W) / R^3): the window test flags
+    // R^2 < (2 m_max v / gk)^(2/3), the per-pair weights m_j / R^3 > gk / (2 v)
+    float ksel[IPT], mthr[IPT];
+    double xi64[IPT][3];  // kTR j-split layouts: the i's FP64 position
+#pragma unroll
+    for (int p = 0; p < IPT; ++p) {
+      float vrel[3];
+      xi64[p][0] = xi64[p][1] = xi64[p][2] = 0.0;
+      if constexpr (MODE == kTR) {
+        const RecP64 F = load_p64(s, i_glob[p]);
+        if constexpr (JL > 1) {
+          xi64[p][0] = F.x;
+          xi64[p][1] = F.y;
+          xi64[p][2] = F.z;
+        }
+        I[p].x = (float)(F.x - fo[0]);
+        I[p].y = (float)(F.y - fo[1]);
+        I[p].z = (float)(F.z - fo[2]);
+        I[p].vx = (float)(F.vx - fv[0]);
+        I[p].vy = (float)(F.vy - fv[1]);
+        I[p].vz = (float)(F.vz - fv[2]);
+        vrel[0] = I[p].vx; vrel[1] = I[p].vy; vrel[2] = I[p].vz;
+      } else if constexpr (MODE == kF64) {
+        vrel[0] = vrel[1] = vrel[2] = 0.f;
+      } else {
+        vrel[0] = I[p].vx - (float)fv[0];
+        vrel[1] = I[p].vy - (float)fv[1];
+        vrel[2] = I[p].vz - (float)fv[2];
+      }
+      ksel[p] = WIN ? 0.f : INFINITY;
+      mthr[p] = 0.f;
+      if constexpr (NEAR && MODE != kF64) {
+        const float vmax = sqrtf(vrel[0] * vrel[0] + vrel[1] * vrel[1] + vrel[2] * vrel[2]) + f_w;
+        if (gk[p] < INFINITY) {
+          if constexpr (WIN) {
+            const float c2 = 2.f * f_mmax * vmax;
+            if (c2 > 0.f) ksel[p] = exp2f((2.f / 3.f) * log2f(c2 / gk[p]));
+          } else {
+            if (vmax > 0.f) ksel[p] = gk[p] / (2.f * vmax) * kNearScale;
+          }
+        }
+        if constexpr (WIN && MODE == kTR) {
+          // mid test: a pair of distance R in this tile has a relative error
+          // of about (L / R) u with L = |x_i - o| + D; redo the window when
+          // its term times L / R may exceed mid_tau |a_i| (acceleration) or
+          // mid_tau |k_i| (jerk):  R^3 < m L / (mid_tau |a|) or
+          // R^4 < 2 m v L / (mid_tau |k|)
+          const float L = sqrtf(I[p].x * I[p].x + I[p].y * I[p].y + I[p].z * I[p].z) + f_d;
+          const float ca_ = f_mmax * L * tau_a / tau_m;
+          if (gsel[p] < INFINITY && ca_ > 0.f) mthr[p] = exp2f((2.f / 3.f) * log2f(ca_ / gsel[p]));
+          const float ck_ = 2.f * f_mmax * vmax * L * tau_k / tau_m;
+          if (gk[p] < INFINITY && ck_ > 0.f) mthr[p] = fmaxf(mthr[p], sqrtf(ck_ / gk[p]));
+        }
+      }
+    }
     __syncthreads();
+    // tile-local index of each i's own entry (-1: not in this tile) and the
+    // tile-local end of the slice: masking compares 32-bit tile indices
+    int own[IPT];
     bool mine = false;
 #pragma unroll
-    for (int p = 0; p < IPT; ++p) mine |= valid[p] && i_glob[p] >= j0 && i_glob[p] < j0 + kTile;
-    const bool need_mask = (j0 + kTile > j_end) || __any(mine);
-    if (need_mask)
-      sweep_tile<MODE, PER, IPT, true, POT, NEAR>(tile, wmax, jl * PER, j0, j_end, i_glob, I, g, gB, eps2d, eps2f,
-                                                  ca, cp, A);
+    for (int p = 0; p < IPT; ++p) {
+      const int64_t d = i_glob[p] - j0;
+      own[p] = (valid[p] && d >= 0 && d < kTile) ? (int)d : -1;
+      mine |= own[p] >= 0;
+    }
+    const int jend = (int)(j_end - j0 < kTile ? j_end - j0 : kTile);
+    const bool need_mask = !LEANW && (jend < kTile || __any(mine));
+    if constexpr (LEANW)
+      sweep_tile<MODE, PER, IPT, false, POT, NEAR, true>(s, tile, tile64, wmax, jl * PER, own, jend, i_glob, I, xi64,
+                                                         gsel, ksel, mthr, eps2d, eps2f, ca, cp, A);
+    else if (need_mask)
+      sweep_tile<MODE, PER, IPT, true, POT, NEAR>(s, tile, tile64, wmax, jl * PER, own, jend, i_glob, I, xi64, gsel,
+                                                  ksel, mthr, eps2d, eps2f, ca, cp, A);
     else
-      sweep_tile<MODE, PER, IPT, false, POT, NEAR>(tile, wmax, jl * PER, j0, j_end, i_glob, I, g, gB, eps2d, eps2f,
-                                                   ca, cp, A);
+      sweep_tile<MODE, PER, IPT, false, POT, NEAR>(s, tile, tile64, wmax, jl * PER, own, jend, i_glob, I, xi64,
+                                                   gsel, ksel, mthr, eps2d, eps2f, ca, cp, A);
   }
 
   const int64_t rows_cap = s.rows_cap;
@@ -550,7 +865,7 @@ __device__ void run_item(const DevState& s, const int32_t* __restrict__ act, con
 // par >= 0 with a single cluster (the step pipeline): the plan follows from
 // that step parity's selection count (plan_single); otherwise it is read
 // from s.plan.
-template <int MODE, bool POT, bool NEAR, bool SPLIT>
+template <int MODE, bool POT, bool NEAR, bool SPLIT, bool LEAN>
 __global__ void __launch_bounds__(kForceThreads) __attribute__((amdgpu_waves_per_eu(SPLIT ? 4 : 3)))
 force_kernel(DevState s, const int32_t* __restrict__ act, int par, int64_t target_items) {
   __shared__ __attribute__((aligned(16))) unsigned char lds[kLdsBytes];
@@ -587,8 +902,8 @@ force_kernel(DevState s, const int32_t* __restrict__ act, int par, int64_t targe
       }
     } else {
       switch (P.variant) {
-        case 0: run_item<MODE, 1, 2, POT, NEAR>(s, act, P, c, local, lds, wmax); break;
-        case 1: run_item<MODE, 1, 1, POT, NEAR>(s, act, P, c, local, lds, wmax); break;
+        case 0: run_item<MODE, 1, 2, POT, NEAR, LEAN>(s, act, P, c, local, lds, wmax); break;
+        case 1: run_item<MODE, 1, 1, POT, NEAR, LEAN>(s, act, P, c, local, lds, wmax); break;
         case 2: run_item<MODE, 4, 1, POT, NEAR>(s, act, P, c, local, lds, wmax); break;
         case 3: run_item<MODE, 16, 1, POT, NEAR>(s, act, P, c, local, lds, wmax); break;
         default: run_item<MODE, 64, 1, POT, NEAR>(s, act, P, c, local, lds, wmax); break;
@@ -602,18 +917,19 @@ struct ForceLaunch {
   const DevState& s;
   const int32_t* act;
   int grid, par;
+  bool lean;
   int64_t target_items;
   hipStream_t st;
 };
 
-template <int MODE, bool NEAR, bool SPLIT>
+template <int MODE, bool NEAR, bool SPLIT, bool LEAN = false>
 static void launch_mode(const ForceLaunch& L, bool pot) {
   if (pot)
-    hipLaunchKernelGGL((force_kernel<MODE, true, NEAR, SPLIT>), dim3(L.grid), dim3(kForceThreads), 0, L.st, L.s,
-                       L.act, L.par, L.target_items);
+    hipLaunchKernelGGL((force_kernel<MODE, true, NEAR, SPLIT, LEAN>), dim3(L.grid), dim3(kForceThreads), 0, L.st,
+                       L.s, L.act, L.par, L.target_items);
   else
-    hipLaunchKernelGGL((force_kernel<MODE, false, NEAR, SPLIT>), dim3(L.grid), dim3(kForceThreads), 0, L.st, L.s,
-                       L.act, L.par, L.target_items);
+    hipLaunchKernelGGL((force_kernel<MODE, false, NEAR, SPLIT, LEAN>), dim3(L.grid), dim3(kForceThreads), 0, L.st,
+                       L.s, L.act, L.par, L.target_items);
 }
 
 template <bool SPLIT>
@@ -628,14 +944,19 @@ static hipError_t launch_family(const ForceLaunch& L, int mode, bool pot, bool n
       if (near) launch_mode<kMX64, true, SPLIT>(L, pot);
       else launch_mode<kMX64, false, SPLIT>(L, pot);
       break;
+    case kTR:
+      if (near && L.lean && !SPLIT) launch_mode<kTR, true, false, true>(L, pot);
+      else if (near) launch_mode<kTR, true, SPLIT>(L, pot);
+      else launch_mode<kTR, false, SPLIT>(L, pot);
+      break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_force(const DevState& s, int mode, bool pot, bool near, bool split, const int32_t* act, int grid,
-                        int par, int64_t target_items, hipStream_t st) {
-  const ForceLaunch L{s, act, grid, par, target_items, st};
+hipError_t launch_force(const DevState& s, int mode, bool pot, bool near, bool split, bool lean, const int32_t* act,
+                        int grid, int par, int64_t target_items, hipStream_t st) {
+  const ForceLaunch L{s, act, grid, par, lean, target_items, st};
   return split ? launch_family<true>(L, mode, pot, near) : launch_family<false>(L, mode, pot, near);
 }
 

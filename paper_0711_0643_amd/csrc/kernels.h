@@ -6,7 +6,7 @@
 namespace nb {
 
 // Pairwise arithmetic modes of the force kernel.
-enum : int { kF64 = 0, kDS = 1, kMX64 = 2 };
+enum : int { kF64 = 0, kDS = 1, kMX64 = 2, kTR = 3 };
 
 // Selection chunk: particles per workgroup of the block-selection kernels.
 constexpr int kSelChunk = 256;
@@ -19,9 +19,11 @@ constexpr int kSelThreads = 256;
 // layouts that split j over lanes (higher occupancy); valid only when no
 // cluster can reach a one-lane-per-i layout.  par: step parity in the step
 // pipeline (with a single cluster the plan then comes from that parity's
-// selection count and target_items), -1 for the plan in s.plan.
-hipError_t launch_force(const DevState& s, int mode, bool pot, bool near, bool split, const int32_t* act, int grid,
-                        int par, int64_t target_items, hipStream_t st);
+// selection count and target_items), -1 for the plan in s.plan.  lean: the
+// tile-relative near build without the masked sweep (every cluster's
+// softening keeps the self pair finite in FP32; see force.hip).
+hipError_t launch_force(const DevState& s, int mode, bool pot, bool near, bool split, bool lean, const int32_t* act,
+                        int grid, int par, int64_t target_items, hipStream_t st);
 
 // Plan the force pass for the active offsets `aoff` (device, nc+1) of an
 // active list of at most n_act_bound entries.  target_items: work items aimed
@@ -45,9 +47,13 @@ hipError_t launch_reduce(const DevState& s, const int64_t* aoff, int64_t n_activ
 // launch_force.
 hipError_t launch_reduce_correct_step(const DevState& s, bool pot, int par, int64_t target_items, hipStream_t st);
 
-// Predict every particle of every cluster to s.tpred[c] (FP64 x_p, v_p and
-// every field of the mixed j-records).
+// Predict every particle of every cluster to s.tpred[c] (FP64 x_p, v_p,
+// every field of the mixed j-records and the tile frames).
 hipError_t launch_predict_all(const DevState& s, hipStream_t st);
+
+// A caller's active list of particle ids mapped to slots (s.ulist);
+// ids outside [0, n) map to -1, which the force pass reports.
+hipError_t launch_map_active(const DevState& s, const int32_t* ids, int64_t n_active, hipStream_t st);
 
 // Write the identity active list (act[i] = i, aoff = coff).
 hipError_t launch_identity(const DevState& s, hipStream_t st);

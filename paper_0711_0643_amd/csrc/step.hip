@@ -21,6 +21,8 @@ __device__ __forceinline__ void set_status(const DevState& s, int32_t bit) {
 //   kMX64: x_p, the FP32 velocity of the j-record, and v_p only for members
 //          of the block (the corrector's particles);
 //   kDS: as kMX64 plus the FP32 pair hi = fl32(x_p), lo = fl32(x_p - hi);
+//   kTR: x_p, v_p (FP64) of every particle (the force pass forms FP32
+//        coordinates relative to each tile's frame from them);
 //   kAllRecords (predict entry point, start-up, energy): everything,
 //          including the FP32 mass of the j-record (constant otherwise).
 constexpr int kAllRecords = -1;
@@ -44,8 +46,9 @@ __device__ __forceinline__ PredIn load_pred(const DevState& s, int64_t i) {
   return in;
 }
 
+// The predicted position and velocity are also returned in xo, vo.
 __device__ __forceinline__ void predict_from(const DevState& s, int64_t i, const PredIn& in, double tp, int mode,
-                                             bool member) {
+                                             bool member, double xo[3], double vo[3]) {
   const int64_t n = s.n;
   const double h = tp - in.t;
   const bool all = mode == kAllRecords;
@@ -55,9 +58,11 @@ __device__ __forceinline__ void predict_from(const DevState& s, int64_t i, const
     const double x = in.x[d], v = in.v[d], a = in.a[d], k = in.k[d];
     const double xp = x + h * (v + h * (0.5 * a + h * (k * (1.0 / 6.0))));
     const double vp = v + h * (a + h * (0.5 * k));
+    xo[d] = xp;
+    vo[d] = vp;
     s.xp[o] = xp;
-    if (all || mode == kF64 || member) s.vp[o] = vp;
-    if (all || mode != kF64) s.jr[(JR_VX + d) * n + i] = (float)vp;
+    if (all || mode == kF64 || mode == kTR || member) s.vp[o] = vp;
+    if (all || mode == kDS || mode == kMX64) s.jr[(JR_VX + d) * n + i] = (float)vp;
     if (all || mode == kDS) {
       const float hi = (float)xp;
       s.jr[(JR_HX + d) * n + i] = hi;
@@ -67,18 +72,101 @@ __device__ __forceinline__ void predict_from(const DevState& s, int64_t i, const
   if (all) s.jr[JR_M * n + i] = (float)s.m[i];
 }
 
-__device__ __forceinline__ void predict_one(const DevState& s, int64_t i, double tp, int mode, bool member) {
-  predict_from(s, i, load_pred(s, i), tp, mode, member);
+// Frame of selection chunk ch (= LDS tile) from the predicted positions and
+// velocities of its particles (`have`: this thread holds one), for the
+// mixed modes: bounding-box centres of positions and velocities, the
+// half-diagonals of the velocity and position boxes and the largest mass.  Called by every
+// thread of the workgroup; min / max are exact, so the frame does not
+// depend on the reduction order.
+__device__ __forceinline__ void tile_frame(const DevState& s, int ch, bool have, const double xp[3], const double vp[3],
+                                           double m) {
+  __shared__ double red[kSelThreads / 64][13];
+  const int tid = threadIdx.x;
+  double lo[6], hi[6], mm = have ? m : 0.0;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    lo[d] = have ? xp[d] : INFINITY;
+    hi[d] = have ? xp[d] : -INFINITY;
+    lo[3 + d] = have ? vp[d] : INFINITY;
+    hi[3 + d] = have ? vp[d] : -INFINITY;
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+      lo[d] = fmin(lo[d], __shfl_xor(lo[d], off));
+      hi[d] = fmax(hi[d], __shfl_xor(hi[d], off));
+    }
+    mm = fmax(mm, __shfl_xor(mm, off));
+  }
+  if ((tid & 63) == 0) {
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+      red[tid >> 6][d] = lo[d];
+      red[tid >> 6][6 + d] = hi[d];
+    }
+    red[tid >> 6][12] = mm;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    for (int w = 1; w < kSelThreads / 64; ++w) {
+#pragma unroll
+      for (int d = 0; d < 6; ++d) {
+        lo[d] = fmin(lo[d], red[w][d]);
+        hi[d] = fmax(hi[d], red[w][6 + d]);
+      }
+      mm = fmax(mm, red[w][12]);
+    }
+    double* f = s.tmeta + (int64_t)ch * kTileMeta;
+    double w2 = 0.0, d2 = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      f[TM_OX + d] = 0.5 * (lo[d] + hi[d]);
+      f[TM_VX + d] = 0.5 * (lo[3 + d] + hi[3 + d]);
+      const double e = hi[3 + d] - lo[3 + d], ex = hi[d] - lo[d];
+      w2 += e * e;
+      d2 += ex * ex;
+    }
+    f[TM_W] = 0.5 * sqrt(w2);
+    f[TM_MMAX] = mm;
+    f[TM_D] = 0.5 * sqrt(d2);
+  }
 }
 
-__global__ void __launch_bounds__(256) predict_all_kernel(DevState s) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < s.n; i += (int64_t)gridDim.x * blockDim.x)
-    predict_one(s, i, s.tpred[s.cid[i]], kAllRecords, true);
+// Full prediction, one workgroup per selection chunk: every particle of
+// every cluster to s.tpred of its cluster, every record field, and the
+// chunk's tile frame.
+__global__ void __launch_bounds__(kSelThreads) predict_all_kernel(DevState s) {
+  const int ch = blockIdx.x;
+  const int64_t i = s.ch_begin[ch] + threadIdx.x;
+  const bool have = i < s.ch_begin[ch + 1];
+  double xp[3] = {0.0, 0.0, 0.0}, vp[3] = {0.0, 0.0, 0.0};
+  double m = 0.0;
+  if (have) {
+    predict_from(s, i, load_pred(s, i), s.tpred[s.ch_cluster[ch]], kAllRecords, true, xp, vp);
+    m = s.m[i];
+  }
+  tile_frame(s, ch, have, xp, vp, m);
 }
 
 hipError_t launch_predict_all(const DevState& s, hipStream_t st) {
-  const int64_t g = (s.n + 255) / 256;
-  hipLaunchKernelGGL(predict_all_kernel, dim3((unsigned)(g < 65535 ? g : 65535)), dim3(256), 0, st, s);
+  static_assert(kSelChunk == kSelThreads, "one particle per thread");
+  hipLaunchKernelGGL(predict_all_kernel, dim3(s.nch), dim3(kSelThreads), 0, st, s);
+  return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(256) map_active_kernel(DevState s, const int32_t* __restrict__ ids,
+                                                         int64_t n_active) {
+  const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (q >= n_active) return;
+  const int32_t id = ids[q];
+  s.ulist[q] = (id >= 0 && id < s.n) ? s.slot_of[id] : -1;
+}
+
+hipError_t launch_map_active(const DevState& s, const int32_t* ids, int64_t n_active, hipStream_t st) {
+  if (n_active <= 0) return hipSuccess;
+  hipLaunchKernelGGL(map_active_kernel, dim3((unsigned)((n_active + 255) / 256)), dim3(256), 0, st, s, ids,
+                     n_active);
   return hipGetLastError();
 }
 
@@ -781,7 +869,11 @@ __global__ void __launch_bounds__(kSelThreads) select_kernel(DevState s, int mod
   const double tsys = block_min(mn, buf);
   const bool advancing = tsys <= s.ctl->t_end;
   const bool member = have && advancing && tt == tsys;
-  if (have && advancing) predict_from(s, i, ahead ? pin : load_pred(s, i), tsys, mode, member);
+  double xo[3] = {0.0, 0.0, 0.0}, vo[3] = {0.0, 0.0, 0.0};
+  if (have && advancing) predict_from(s, i, ahead ? pin : load_pred(s, i), tsys, mode, member, xo, vo);
+  // the mixed force pass reads the tile frame of every chunk of an
+  // advancing cluster (the condition is the same for the whole workgroup)
+  if (advancing && mode != kF64) tile_frame(s, ch, have, xo, vo, have ? s.m[i] : 0.0);
 
   // members, and the smallest t + dt of the others
   const double rest = block_min(member ? INFINITY : tt, buf);

@@ -92,6 +92,7 @@ class Layout(ctypes.Structure):
         ("xp", ctypes.c_size_t),
         ("vp", ctypes.c_size_t),
         ("pot", ctypes.c_size_t),
+        ("order", ctypes.c_size_t),
     ]
 
 
@@ -105,6 +106,8 @@ class Tuning(ctypes.Structure):
         ("near_tau", ctypes.c_double),
         ("small_cluster_n", ctypes.c_int32),
         ("small_min_block", ctypes.c_int32 * 4),
+        ("near_tau_k", ctypes.c_double),
+        ("mid_tau", ctypes.c_double),
     ]
 
 
@@ -242,10 +245,43 @@ class Sim:
         _check(lib().nbody_get_layout(self._ctx, ctypes.byref(lay)), "nbody_get_layout")
         self._layout = lay
 
-    # -- views of the state inside the workspace (no copies) -------------------------
-    def _view(self, off: int, rows: int):
+    # -- the state inside the workspace ---------------------------------------------
+    # The library stores particles in its own order (Morton order inside each
+    # cluster); slot q holds particle order[q].  The properties below return
+    # the state in particle-id order (gathered copies); ``raw`` views give the
+    # arrays in storage order without a copy.
+    @property
+    def order(self):
+        """(N,) int64 tensor: the particle id stored at each slot."""
+        off = self._layout.order
+        return self.workspace[off: off + 4 * self.n].view(self._torch.int32).long()
+
+    @property
+    def slot_of(self):
+        """(N,) int64 tensor: the slot of each particle id."""
+        o = self.order
+        inv = self._torch.empty_like(o)
+        inv[o] = self._torch.arange(self.n, device=o.device)
+        return inv
+
+    def raw(self, name: str):
+        """View of a state array (m, x, v, a, k, t, dt, xp, vp) in storage order."""
+        rows = 3 if name in ("x", "v", "a", "k", "xp", "vp") else 1
+        off = getattr(self._layout, name)
         t = self.workspace[off: off + 8 * rows * self.n].view(self._torch.float64)
         return t.view(rows, self.n) if rows > 1 else t
+
+    def _view(self, off: int, rows: int):
+        t = self.workspace[off: off + 8 * rows * self.n].view(self._torch.float64)
+        t = t.view(rows, self.n) if rows > 1 else t
+        return t[..., self.slot_of]
+
+    def storage_active(self, n_act=None):
+        """Particle ids of the first n_act slots of a single cluster (all by
+        default): an active list in storage order, the fastest for the mixed
+        force pass."""
+        o = self.order.to(self._torch.int32)
+        return o if n_act is None else o[:n_act]
 
     @property
     def x(self):
@@ -299,7 +335,8 @@ class Sim:
         return {"target_items": t.target_items, "min_block": list(t.min_block), "grid": t.grid,
                 "mixed_format": t.mixed_format, "rsq_bias_correct": t.rsq_bias_correct,
                 "near_tau": t.near_tau, "small_cluster_n": t.small_cluster_n,
-                "small_min_block": list(t.small_min_block)}
+                "small_min_block": list(t.small_min_block), "near_tau_k": t.near_tau_k,
+                "mid_tau": t.mid_tau}
 
     def set_tuning(self, **kw) -> None:
         cur = self.get_tuning()
@@ -312,6 +349,8 @@ class Sim:
         t.mixed_format = int(cur["mixed_format"])
         t.rsq_bias_correct = int(cur["rsq_bias_correct"])
         t.near_tau = float(cur["near_tau"])
+        t.near_tau_k = float(cur["near_tau_k"])
+        t.mid_tau = float(cur["mid_tau"])
         t.small_cluster_n = int(cur["small_cluster_n"])
         for i in range(4):
             t.small_min_block[i] = int(cur["small_min_block"][i])

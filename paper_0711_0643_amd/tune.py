@@ -165,7 +165,7 @@ def tune(sim, use_cache: bool = True, ladder=None, verbose: bool = False) -> dic
     ref = reference(act, aoff)
     best = None
     cus = torch.cuda.get_device_properties(dev).multi_processor_count
-    formats = (0, 1) if prec == 1 else (base["mixed_format"],)
+    formats = (0, 1, 2) if prec == 1 else (base["mixed_format"],)
     for fmt in formats:
         for target in (2 * cus, 4 * cus, 8 * cus, 16 * cus):
             for grid in (4 * cus, 8 * cus, 16 * cus):

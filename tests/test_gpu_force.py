@@ -8,12 +8,16 @@ Tolerances:
                   (summation order and FMA differ from the oracle's plain
                   j-ascending loop; 1e-12 leaves room for cancellation).
   mixed kernel -- acceleration and potential: per particle relative error
-                  <= 1e-6 (the force-error bar); jerk: error measured against
-                  the sum of absolute jerk terms K_i <= 1e-6.  FP32 pair terms
-                  carry a few units of u = 2^-24 each (about 3e-7), so the
-                  jerk error is bounded by ~5 u K_i; its relative error
-                  |dk|/|k| then scales with the cancellation K_i/|k_i|, which
-                  reaches ~50 in a Plummer sphere.
+                  <= 1e-6 (the force-error bar).  Jerk: per particle relative
+                  error <= 1e-6 for every particle whose jerk cancellation
+                  kappa_k = K_i/|k_i| (K_i = sum of |jerk term|) is at most
+                  10; every particle, whatever its kappa_k, within 1e-6 K_i.
+                  FP32 pair terms carry a few units of u = 2^-24 each, so
+                  the relative jerk error of a particle with strong
+                  cancellation scales with kappa_k, which reaches a few
+                  hundred in a Plummer sphere; those particles are counted
+                  and reported by the benchmark rather than held to the
+                  relative bar.
 """
 import numpy as np
 import pytest
@@ -56,6 +60,10 @@ def _check_mixed(got, ref, absum):
     assert ea.max() <= 1e-6, ea.max()
     ek_norm = normwise_err(k, rk, absum[1])
     assert ek_norm.max() <= 1e-6, ek_norm.max()
+    kappa = absum[1] / np.maximum(np.linalg.norm(rk, axis=0), 1e-300)
+    ek = rel_err(k, rk)
+    low = kappa <= 10
+    assert not low.any() or ek[low].max() <= 1e-6, (ek[low].max(), int((ek[low] > 1e-6).sum()))
     if p is not None:
         assert rel_err(p, rp).max() <= 1e-6, rel_err(p, rp).max()
 
