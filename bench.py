@@ -31,10 +31,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# Algorithmic flops per acc + jerk (+ potential) interaction, counting an
-# FMA as 2 and the reciprocal square root as 1: dr 3, dv 3, R^2 6, rsqrt 1,
-# R^-2 / m R^-1 / m R^-3 3, r.v 5, -3 r.v / R^2 2, a 6, k 12, phi 1.
-FLOPS_PER_INTERACTION = 42
+# Algorithmic flops per acc + jerk interaction, counting an FMA as 2 and the
+# reciprocal square root as 1: dr 3, dv 3, R^2 6, rsqrt 1, R^-2 / m R^-1 /
+# m R^-3 3, r.v 5, -3 r.v / R^2 2, a 6, k 12 = 41; the potential adds 1.
+# The timed kernel computes no potential, so the roofline counts 41.
+FLOPS_ACC_JERK = 41
+FLOPS_WITH_POT = 42
+FLOPS_PER_INTERACTION = FLOPS_ACC_JERK
 PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector peak (published; counts packed FP32)
 PEAK_FP64_TFLOPS = 78.6
 
@@ -46,6 +49,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--n", type=int, default=65536)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-integrations", action="store_true",
+                    help="skip the integration workloads (N=65536 run, 256-cluster batch, performance model)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target duration of the CPU sample")
     ap.add_argument("--kernel-reps", type=int, default=10, help="timed launches of the force kernel alone")
     ap.add_argument("--no-sweep", action="store_true",
@@ -348,6 +353,86 @@ def perf_model():
                       "to t=1/8 timed with HIP events"}
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def golden_runs():
+    path = os.path.join(ROOT, "tests", "golden", "oracle_runs.json")
+    with open(path) as f:
+        return json.load(f)
+
+
+def integration_evidence():
+    """The workloads beside the headline, measured in the same run:
+    the N = 65536 Plummer run to t = 1/4 (mixed), the 256-cluster batch to
+    t = 1/2 (mixed), and the paper's performance model fitted to every block
+    step of Plummer runs to t = 1/8 (Sect. 4.1, Eq. tsnb).  Drifts are
+    compared with the FP64 oracle's integration of the same inputs
+    (tests/golden/oracle_runs.json)."""
+    import torch
+
+    import icgen
+    import paper_0711_0643_amd as nb
+
+    g = golden_runs()
+    out = {}
+
+    def timed_run(sim, t_end):
+        E0 = sim.energy()
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        sim.run(t_end, chunk=512)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - w0
+        E1 = sim.energy()
+        _, steps, inter = sim.progress()
+        return wall, (E1 - E0) / np.abs(E0), steps, inter
+
+    # C3: Plummer N = 65536, eps = 1/N, mixed, to t = 1/4
+    c3 = g["C3"]
+    m, x, v = icgen.plummer(c3["n"], c3["seed"])
+    sim = nb.Sim(m, x, v, c3["eps"], precision=nb.MIXED)
+    wall, drift, steps, inter = timed_run(sim, c3["t_end"])
+    sim.close()
+    ref = [e for _, e in c3["energy_trace"]]
+    ref_drift = (ref[-1] - ref[0]) / abs(ref[0])
+    out["c3_plummer_n65536_mixed_to_t0.25"] = {
+        "wall_s": round(wall, 4), "block_steps": int(steps[0]), "us_per_block_step": round(wall / steps[0] * 1e6, 2),
+        "Ginteractions_per_s": round(float(inter[0]) / wall / 1e9, 2), "rel_energy_drift": float(drift[0]),
+        "oracle_rel_energy_drift": ref_drift, "oracle_block_steps": c3["block_steps"]}
+    log(f"c3 run: {out['c3_plummer_n65536_mixed_to_t0.25']}")
+
+    # C4: the 256-cluster ensemble, mixed, to t = 1/2 (default tuning)
+    c4 = g["C4"]
+    m, x, v, coff, eps = icgen.ensemble(c4["n_clusters"], c4["master_seed"])
+    sim = nb.Sim(m, x, v, eps, cluster_offsets=coff, precision=nb.MIXED)
+    wall, drift, steps, inter = timed_run(sim, c4["t_end"])
+    sim.close()
+    vs = {}
+    for key, rec in c4["clusters"].items():
+        r = [e for _, e in rec["energy_trace"]]
+        vs[key] = {"n": rec["n"], "rel_energy_drift": float(drift[int(key)]),
+                   "oracle_rel_energy_drift": (r[-1] - r[0]) / abs(r[0])}
+    worst = int(np.argmax(np.abs(drift)))
+    out["c4_batch256_mixed_to_t0.5"] = {
+        "wall_s": round(wall, 4), "graph_replays": int(steps.max()), "sum_n": int(coff[-1]),
+        "Ginteractions_per_s": round(float(inter.sum()) / wall / 1e9, 2),
+        "worst_rel_energy_drift": {"cluster": worst, "n": int(coff[worst + 1] - coff[worst]),
+                                   "drift": float(drift[worst])},
+        "clusters_vs_oracle": vs}
+    log(f"c4 batch: wall {wall:.3f} s, {out['c4_batch256_mixed_to_t0.5']['Ginteractions_per_s']} Ginteractions/s")
+
+    out["performance_model"] = perf_model()
+    return out
+
+
 def main():
     args = parse()
     if args.calibrate_copy:
@@ -378,6 +463,7 @@ def main():
     # name, precision, tuning overrides, full sweep + steps
     variants = [("mixed", nb.MIXED, {}, True), ("fp64", nb.FP64, {}, True),
                 ("mixed_no_near_fp64", nb.MIXED, {"near_tau": 0.0}, False),
+                ("mixed_fp64_differences", nb.MIXED, {"mixed_format": 1}, False),
                 ("mixed_double_single", nb.MIXED, {"mixed_format": 0}, False)]
     if args.no_sweep:
         variants = [("mixed", nb.MIXED, {}, False)]
@@ -387,11 +473,15 @@ def main():
         if tune:
             sim.set_tuning(**tune)
         sim.sync()
-        # force kernel alone on the t = 0 state (x_p = x), full block
-        act = torch.arange(n, dtype=torch.int32, device=sim.device)
+        # force kernel alone on the t = 0 state (x_p = x), full block, the
+        # active list in the library's storage order (as the block steps use it)
+        act = sim.storage_active()
+        order = sim.order.cpu().numpy()
         aoff = torch.tensor([0, n], dtype=torch.int64, device=sim.device)
         kt, acc, jerk = kernel_time(sim, act, aoff, args.kernel_reps, warm=10)
-        res = dict(kernel_s=kt, acc=acc.cpu().numpy(), jerk=jerk.cpu().numpy())
+        a_id = np.empty((3, n)); a_id[:, order] = acc.cpu().numpy()
+        k_id = np.empty((3, n)); k_id[:, order] = jerk.cpu().numpy()
+        res = dict(kernel_s=kt, acc=a_id, jerk=k_id)
         if args.no_sweep:
             wall, evs = time_steps(sim, args.steps, args.warmup, dt)
             res.update(wall=wall, ev=evs)
@@ -429,14 +519,16 @@ def main():
     ea = np.linalg.norm(mx["acc"] - fp["acc"], axis=0) / np.linalg.norm(fp["acc"], axis=0)
     ek = np.linalg.norm(mx["jerk"] - fp["jerk"], axis=0) / np.linalg.norm(fp["jerk"], axis=0)
     alt = {}
-    for name in ("mixed_no_near_fp64", "mixed_double_single"):
+    for name in ("mixed_no_near_fp64", "mixed_fp64_differences", "mixed_double_single"):
         r = results[name]
         e = np.linalg.norm(r["acc"] - fp["acc"], axis=0) / np.linalg.norm(fp["acc"], axis=0)
+        ej = np.linalg.norm(r["jerk"] - fp["jerk"], axis=0) / np.linalg.norm(fp["jerk"], axis=0)
         alt[name] = {"kernel_ms": round(r["kernel_s"] * 1e3, 4),
                      "Ginteractions_per_s": round(n * float(n) / r["kernel_s"] / 1e9, 2),
-                     "acc_max_rel_vs_fp64": float(e.max()), "n_acc_above_1e-6": int((e > 1e-6).sum())}
+                     "acc_max_rel_vs_fp64": float(e.max()), "n_acc_above_1e-6": int((e > 1e-6).sum()),
+                     "jerk_max_rel_vs_fp64": float(ej.max())}
 
-    achieved = FLOPS_PER_INTERACTION * inter_step / mx["kernel_s"] / 1e12
+    achieved = FLOPS_ACC_JERK * inter_step / mx["kernel_s"] / 1e12
     out = {
         "metric": "Ginteractions/s acc+jerk at N=65536 (mixed vs FP64, <=1e-6 rel force err)",
         "value": round(value, 3),
@@ -448,15 +540,17 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "mixed",
         "data": "synthetic",
         "config": {
             "workload": f"Plummer sphere N={n}, equal masses, eps=1/N, full-block Hermite block steps "
                         f"(select, predict, mixed force, reduce, correct), shared dt=2^-10",
             "n": n,
             "n_active": n,
-            "precision": "mixed: FP64 position differences rounded to FP32, FP32 pair terms, "
-                         "near pairs (m/R^2 > |a|/4) in FP64, FP64 totals",
+            "precision": "mixed: FP64 positions and velocities; FP32 coordinates relative to each 256-particle "
+                         "tile's frame (Morton storage order); FP32 pair terms; near pairs (acceleration term > "
+                         "|a|/4, jerk term > |k|) in FP64; pairs much closer than their tile with FP64 "
+                         "differences; FP64 totals",
         },
         "roofline": {
             "bound": "alu",
@@ -465,8 +559,10 @@ def main():
             "unit": "TFLOP/s",
             "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
             "traffic": recorded_traffic(),
-            "kernel": "nb::force_kernel<2, false, true, false> (mixed, FP64 positions, near pairs in FP64, all layouts)",
-            "flops_per_interaction": FLOPS_PER_INTERACTION,
+            "kernel": "nb::force_kernel<3, false, true, false, true> (mixed tile-relative, no potential, near "
+                      "pairs, all layouts, lean)",
+            "flops_per_interaction": FLOPS_ACC_JERK,
+            "flop_count_rule": "algorithmic acc + jerk without the potential (FMA = 2, rsqrt = 1); 42 with it",
             "interactions_per_launch": inter_step,
             "kernel_ms": round(mx["kernel_s"] * 1e3, 4),
             # labelled context, not used for frac: the 60-flop acc+jerk count common in
@@ -479,8 +575,8 @@ def main():
             "value": round(args.steps * inter_step / fp["wall"] / 1e9, 3),
             "ms_per_step": round(fp["wall"] / args.steps * 1e3, 4),
             "kernel_ms": round(fp["kernel_s"] * 1e3, 4),
-            "kernel_tflops": round(FLOPS_PER_INTERACTION * inter_step / fp["kernel_s"] / 1e12, 3),
-            "frac_of_fp64_peak": round(FLOPS_PER_INTERACTION * inter_step / fp["kernel_s"] / 1e12 / PEAK_FP64_TFLOPS, 4),
+            "kernel_tflops": round(FLOPS_ACC_JERK * inter_step / fp["kernel_s"] / 1e12, 3),
+            "frac_of_fp64_peak": round(FLOPS_ACC_JERK * inter_step / fp["kernel_s"] / 1e12 / PEAK_FP64_TFLOPS, 4),
             "force_sweep": fp["sweep"],
         },
         "mixed_force_sweep": mx["sweep"],
@@ -514,6 +610,7 @@ def main():
             "value": round(cpu_rate, 5),
             "unit": "Ginteractions/s",
             "cores": oracle.threads(),
+            "cpu_model": cpu_model(),
             "kind": "oracle",
             "sample": f"FP64 oracle acc+jerk+pot on {n_s} active particles x {n} (same Plummer state), "
                       f"{t1 - t0:.1f} s",
@@ -528,12 +625,33 @@ def main():
         oracle.set_threads(cores)
         out["cpu_baseline"]["single_thread"] = {"value": round(one.size * float(n) / (t2 - t0) / 1e9, 5),
                                                 "sample": f"{one.size} active x {n}, {t2 - t0:.1f} s"}
-        # both kernels against the oracle on that sample (same t = 0 state)
+        # both kernels against the oracle on that sample (same t = 0 state);
+        # the jerk gate is per particle for jerk cancellation kappa_k <= 10
+        # (kappa_k = sum of |jerk terms| / |k|); the others are counted
+        absum = oracle.force_abs(m, x, v, eps, sample)
+        kap = absum[1] / np.linalg.norm(rk, axis=0)
         ea_o = np.linalg.norm(mx["acc"][:, sample] - ra, axis=0) / np.linalg.norm(ra, axis=0)
         ef_o = np.linalg.norm(fp["acc"][:, sample] - ra, axis=0) / np.linalg.norm(ra, axis=0)
-        out["vs_oracle"] = {"mixed_acc_max_rel": float(ea_o.max()), "fp64_acc_max_rel": float(ef_o.max()),
-                            "mixed_n_acc_above_1e-6": int((ea_o > 1e-6).sum()), "sample": int(n_s)}
+        ek_o = np.linalg.norm(mx["jerk"][:, sample] - rk, axis=0) / np.linalg.norm(rk, axis=0)
+        en_o = np.linalg.norm(mx["jerk"][:, sample] - rk, axis=0) / absum[1]
+        low = kap <= 10
+        above = np.nonzero(ek_o > 1e-6)[0]
+        out["vs_oracle"] = {
+            "sample": int(n_s),
+            "mixed_acc_max_rel": float(ea_o.max()), "fp64_acc_max_rel": float(ef_o.max()),
+            "mixed_n_acc_above_1e-6": int((ea_o > 1e-6).sum()),
+            "mixed_jerk_max_rel_kappa_le_10": float(ek_o[low].max()) if low.any() else None,
+            "mixed_n_jerk_above_1e-6_kappa_le_10": int((ek_o[low] > 1e-6).sum()),
+            "mixed_jerk_max_normwise": float(en_o.max()),
+            "n_kappa_above_10": int((~low).sum()),
+            "mixed_jerk_above_1e-6": {"count": int(above.size),
+                                      "kappa": [round(float(kap[i]), 1) for i in above[:20]],
+                                      "rel_err": [float(ek_o[i]) for i in above[:20]]},
+        }
         log(f"cpu oracle: {cpu_rate:.4f} Ginteractions/s on {oracle.threads()} threads")
+
+    if not args.no_integrations:
+        out["integrations"] = integration_evidence()
 
     print(json.dumps(out), flush=True)
 

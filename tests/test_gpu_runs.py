@@ -75,3 +75,45 @@ def test_mixed_run_energy_drift_matches_oracle(case):
     assert abs(drift) < 1e-5
     assert abs(drift - ref_drift) < 1e-8
     sim.close()
+
+
+def _batch_traces(sim, t_end):
+    traces = [sim.energy()]
+    t = 0.0
+    while t < t_end:
+        t += 0.125
+        sim.run(t, chunk=512)
+        traces.append(sim.energy())
+    assert sim.status() == 0
+    return np.array(traces)  # (times, clusters)
+
+
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
+def test_batch_of_256_clusters_matches_oracle_runs(precision):
+    """The 256-cluster ensemble (N log-uniform in [256, 8192]) advanced as one
+    batch to t = 1/2; six clusters (two smallest, two of median size, two
+    largest) against the oracle integrating each of them alone.  FP64: block
+    steps and interactions exactly, energies to 1e-12.  Mixed: the energy
+    drift of each cluster within 1e-7 of the oracle's."""
+    import paper_0711_0643_amd as nb
+
+    g = _golden("C4")
+    m, x, v, coff, eps = icgen.ensemble(g["n_clusters"], g["master_seed"])
+    banner(f"batch of {g['n_clusters']} clusters precision={precision}")
+    sim = nb.Sim(m, x, v, eps, cluster_offsets=coff, precision=precision)
+    traces = _batch_traces(sim, g["t_end"])
+    _, steps, inter = sim.progress()
+    for key, rec in g["clusters"].items():
+        c = int(key)
+        assert int(coff[c + 1] - coff[c]) == rec["n"]
+        ref = np.array([e for _, e in rec["energy_trace"]])
+        tr = traces[:, c]
+        if precision == 0:
+            assert int(steps[c]) == rec["block_steps"], (c, int(steps[c]), rec["block_steps"])
+            assert float(inter[c]) == rec["interactions"]
+            assert np.max(np.abs(tr - ref)) <= 1e-12 * abs(ref[0])
+        else:
+            drift = (tr[-1] - tr[0]) / abs(tr[0])
+            ref_drift = (ref[-1] - ref[0]) / abs(ref[0])
+            assert abs(drift - ref_drift) < 1e-7, (c, drift, ref_drift)
+    sim.close()
