@@ -28,6 +28,9 @@
  *     nothing.  Errors detected on the device (step underflow, non-finite
  *     values, out-of-range indices) are recorded in a status word in the
  *     workspace, returned by nbody_sync and by the next call that reads it.
+ *     Once the status word holds an error, the state is frozen: every later
+ *     block step of nbody_step selects nothing and leaves every array and
+ *     counter bitwise unchanged, until nbody_set_state restores a state.
  *   - A context is bound to one stream and is not thread-safe.
  *
  * Readings of the paper the library implements (the paper does not spell
@@ -156,10 +159,15 @@ NBODY_API nbody_status nbody_correct(nbody_ctx *ctx, const int32_t *active_idx,
  * new steps).  Each step advances every cluster whose time is below t_end by
  * exactly one of its own block steps; clusters at t_end stay put.  t_end
  * must be a multiple of dt_max.  Runs as captured HIP graphs (runs of 32
- * steps and single steps), replayed without host synchronisation. */
+ * steps and single steps), replayed without host synchronisation.
+ * Device errors freeze the state (see above): the step in which a new step
+ * falls below dt_min completes, later ones change nothing.  Once the host
+ * has read an error (nbody_sync), nbody_step returns it and enqueues
+ * nothing. */
 NBODY_API nbody_status nbody_step(nbody_ctx *ctx, int32_t n_block_steps, double t_end);
 
-/* Waits for the context's stream; returns the first device-side error. */
+/* Waits for the context's stream; returns the first device-side error
+ * (the status word is sticky: it is returned again until nbody_set_state). */
 NBODY_API nbody_status nbody_sync(nbody_ctx *ctx);
 
 /* Per-cluster softened energy E = sum m v^2/2 + (1/2) sum m phi in FP64,
@@ -185,7 +193,8 @@ NBODY_API nbody_status nbody_progress(nbody_ctx *ctx, double *t_host, int64_t *s
 /* Checkpoint: bytes of the state blob, and copies of the full FP64 state
  * (m, x, v, a, k, t, dt, softening, cluster times and counters) to / from a
  * host buffer.  Synchronous.  Restoring and continuing gives the same bits
- * as an uninterrupted run. */
+ * as an uninterrupted run.  nbody_set_state also clears the recorded device
+ * errors (e.g. restore the last good checkpoint, lower dt_min, continue). */
 NBODY_API nbody_status nbody_state_bytes(const nbody_ctx *ctx, size_t *bytes);
 NBODY_API nbody_status nbody_get_state(nbody_ctx *ctx, void *host_buf, size_t bytes);
 NBODY_API nbody_status nbody_set_state(nbody_ctx *ctx, const void *host_buf, size_t bytes);

@@ -9,6 +9,12 @@ PyTorch providing device memory and streams.
 from .nbody import (  # noqa: F401
     FP64,
     MIXED,
+    NBODY_E_DTMIN,
+    NBODY_E_INDEX,
+    NBODY_E_INVAL,
+    NBODY_E_NONFINITE,
+    NBODY_E_STATE,
+    NBODY_OK,
     NBodyError,
     Params,
     Sim,

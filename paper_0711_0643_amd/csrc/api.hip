@@ -181,6 +181,9 @@ struct nbody_ctx {
   // the step pipeline's selection state (chunk minima, unit minima, plan)
   // matches t, dt; cleared by every call that changes them outside the graph
   bool sel_valid = false;
+  // device status bits the host has read (nbody_sync); nbody_step returns
+  // them without enqueuing work until nbody_set_state restores a state
+  int32_t seen_bits = 0;
   std::vector<int64_t> coff;
   std::vector<int32_t> order;  // particle id stored at each slot
   // every cluster keeps the self pair of the mixed kernel finite in FP32
@@ -600,6 +603,9 @@ nbody_status nbody_correct(nbody_ctx* c, const int32_t* active_idx, const int64_
 nbody_status nbody_step(nbody_ctx* c, int32_t n_block_steps, double t_end) {
   if (!c || n_block_steps < 0 || !(t_end >= 0.0) || !isfinite(t_end)) return NBODY_E_INVAL;
   if (fmod(t_end, c->p.dt_max) != 0.0) return NBODY_E_INVAL;
+  // a device error the host has already read: the state is frozen (the
+  // selection kernel takes no step while the status word holds an error)
+  if (c->seen_bits) return status_from_bits(c->seen_bits);
   if (n_block_steps == 0) return NBODY_OK;
   if (!c->gexec_k || c->graph_mode != force_mode(c) || c->graph_pot != c->p.compute_pot) {
     const nbody_status r = build_graph(c);
@@ -635,6 +641,7 @@ nbody_status nbody_sync(nbody_ctx* c) {
   HIP_OK(hipStreamSynchronize(c->stream));
   int32_t bits = 0;
   HIP_OK(hipMemcpy(&bits, c->s.status, sizeof(int32_t), hipMemcpyDeviceToHost));
+  c->seen_bits |= bits;
   return status_from_bits(bits);
 }
 
@@ -735,7 +742,10 @@ nbody_status nbody_set_state(nbody_ctx* c, const void* host_buf, size_t bytes) {
     HIP_OK(hipMemcpyAsync(c->ws + p.off, h + o, p.bytes, hipMemcpyHostToDevice, c->stream));
     o += p.bytes;
   }
+  // a restored state starts with no recorded device error
+  HIP_OK(hipMemsetAsync(c->s.status, 0, sizeof(int32_t), c->stream));
   HIP_OK(hipStreamSynchronize(c->stream));
+  c->seen_bits = 0;
   c->sel_valid = false;
   // the prediction no longer matches the state
   HIP_OK(hipMemcpyAsync(c->s.tpred, c->s.tnow, 8 * (size_t)c->nc, hipMemcpyDeviceToDevice, c->stream));

@@ -779,7 +779,8 @@ hipError_t launch_correct(const DevState& s, const int32_t* act, const int64_t* 
 // the cluster's own segment of the active list (starting at coff[c]) through
 // an atomic counter; their order there does not change any particle's sums.
 // Every particle of an advancing cluster is predicted.  A cluster whose
-// block time is past t_end takes no step.
+// block time is past t_end takes no step, and none does once the status word
+// holds an error.
 //
 // The chunk minima (cm2) and the counters (acount) have one half per step
 // parity `par`, a launch argument that the captured graphs alternate: step k
@@ -867,7 +868,12 @@ __global__ void __launch_bounds__(kSelThreads) select_kernel(DevState s, int mod
     for (int64_t u = tid; u < units; u += kSelThreads) mn = fmin(mn, s.umin[P.red_off + u]);
   }
   const double tsys = block_min(mn, buf);
-  const bool advancing = tsys <= s.ctl->t_end;
+  // an error recorded on the device (step underflow, non-finite value, bad
+  // index) freezes the state: no cluster advances, so this step and every
+  // later one select nothing and change nothing; the status word was written
+  // by earlier kernels only, so every workgroup reads the same value
+  const bool frozen = *s.status != 0;
+  const bool advancing = !frozen && tsys <= s.ctl->t_end;
   const bool member = have && advancing && tt == tsys;
   double xo[3] = {0.0, 0.0, 0.0}, vo[3] = {0.0, 0.0, 0.0};
   if (have && advancing) predict_from(s, i, ahead ? pin : load_pred(s, i), tsys, mode, member, xo, vo);

@@ -19,16 +19,16 @@ _LIB_PATH = _PKG / "libnbody.so"
 FP64 = 0
 MIXED = 1
 
-_STATUS = {
-    0: "NBODY_OK",
-    -1: "NBODY_E_INVAL",
-    -2: "NBODY_E_NOMEM",
-    -3: "NBODY_E_HIP",
-    -4: "NBODY_E_STATE",
-    -5: "NBODY_E_DTMIN",
-    -6: "NBODY_E_NONFINITE",
-    -7: "NBODY_E_INDEX",
-}
+# nbody_status codes (include/nbody.h)
+NBODY_OK = 0
+NBODY_E_INVAL = -1
+NBODY_E_NOMEM = -2
+NBODY_E_HIP = -3
+NBODY_E_STATE = -4
+NBODY_E_DTMIN = -5
+NBODY_E_NONFINITE = -6
+NBODY_E_INDEX = -7
+_STATUS = {code: name for name, code in list(globals().items()) if name.startswith("NBODY_")}
 
 EXPORTED = [
     "nbody_default_params",

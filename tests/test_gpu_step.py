@@ -309,6 +309,70 @@ def test_status_reports_step_underflow():
     sim.close()
 
 
+@pytest.mark.parametrize("case", ["single_mixed", "batch_fp64"])
+def test_device_error_freezes_the_state(case):
+    """After a new step falls below dt_min, later block steps change nothing.
+    A run stepped one block step at a time finds the failing step; the state
+    after it is bitwise the state after many more steps enqueued at once,
+    before the host has read the error (the device freezes itself), and
+    nbody_step returns the error once nbody_sync has read it.  Restoring an
+    earlier checkpoint clears the error and the run continues."""
+    import paper_0711_0643_amd as nb
+
+    if case == "single_mixed":
+        m, x, v = icgen.plummer(1024, 41)
+        eps, coff, prec = 1.0 / 1024, None, 1
+    else:
+        m, x, v, coff, eps = icgen.ensemble(3, 14, 300, 900)
+        prec = 0
+    t_end = 0.25
+    banner(f"device error freezes the state {case}")
+
+    def prefix():
+        sim = _sim(m, x, v, eps, precision=prec, coff=coff)
+        sim.step(150, t_end)
+        assert sim.status() == 0
+        good = sim.get_state()
+        dt_floor = float(sim.host_state()["dt"].min())
+        # every particle with a step this small fails at its next correction
+        sim.set_params(dt_min=4.0 * dt_floor)
+        return sim, good
+
+    a, good = prefix()
+    k = 0
+    while k < 4000:
+        a.step(1, t_end)
+        k += 1
+        if a.status() != 0:
+            break
+    assert a.status() == nb.NBODY_E_DTMIN, k
+    frozen = a.get_state()
+    prog = a.progress()
+    with pytest.raises(nb.NBodyError) as err:
+        a.step(8, t_end)
+    assert err.value.code == nb.NBODY_E_DTMIN
+    assert a.get_state() == frozen
+
+    b, _ = prefix()
+    b.step(k + 70, t_end)  # the error has not been read yet: enqueued
+    assert b.status() == nb.NBODY_E_DTMIN
+    assert b.get_state() == frozen
+    for u, w in zip(prog, b.progress()):
+        assert np.array_equal(u, w)
+
+    # recovery: the checkpoint before the failure, the original floor
+    b.set_state(good)
+    b.set_params(dt_min=2.0**-40)
+    b.step(20, t_end)
+    assert b.status() == 0
+    ref = _sim(m, x, v, eps, precision=prec, coff=coff)
+    ref.step(150, t_end)
+    ref.step(20, t_end)
+    assert ref.get_state() == b.get_state()
+    for s_ in (a, b, ref):
+        s_.close()
+
+
 def test_api_calls_between_steps_leave_the_run_unchanged():
     """The step pipeline carries the next block time over from one step to
     the next; calls that replace the plan or read the state in between
