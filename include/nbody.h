@@ -145,6 +145,28 @@ NBODY_API nbody_status nbody_predict(nbody_ctx *ctx, const double *t_pred);
 NBODY_API nbody_status nbody_force(nbody_ctx *ctx, const int32_t *active_idx, const int64_t *active_offsets,
                          int64_t n_active, double *acc, double *jerk, double *pot);
 
+/* nbody_force for callers that cannot allocate device memory or must not
+ * touch the context's workspace beyond its state (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * arguments, kernels and results, bit for bit, but the slice partial sums of
+ * the force pass go to a static device array of the library (64 MiB, one per
+ * GPU, held until the process ends) instead of the workspace.  Allocates
+ * nothing: no hipMalloc, hipFree or allocating library call.
+ * Limit: the pass may plan at most 1198372 partial rows (7 FP64 each); a
+ * call that could exceed it returns NBODY_E_INVAL and enqueues nothing.  It
+ * is accepted whenever n_active * ceil(N_max / 256) <= 1198372 (N_max: the
+ * largest cluster) or n_clusters * target_items * 512 + n_active <= 1198372
+ * (e.g. any block of a single cluster of up to 65536 particles at the
+ * default target_items 2048).
+ * Every call on one GPU, from any context, shares that array, and the
+ * array keeps the last call's contents: calls that overlap on one GPU (on
+ * different streams) race and give wrong results.  NBODY_E_HIP if the
+ * library could not look up the array's address on the context's device
+ * at nbody_init. */
+NBODY_API nbody_status nbody_force_noalloc(nbody_ctx *ctx, const int32_t *active_idx,
+                                 const int64_t *active_offsets, int64_t n_active, double *acc,
+                                 double *jerk, double *pot);
+
 /* Hermite corrector, Aarseth step and block quantisation (Sect. 2.1) for the
  * listed particles, advancing each to its cluster's last predicted time
  * (the prediction time of nbody_predict, or of the last block step).

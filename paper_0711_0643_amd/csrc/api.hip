@@ -12,6 +12,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <utility>
 #include <vector>
@@ -22,7 +23,37 @@
 
 using namespace nb;
 
+// Device scratch of nbody_force_noalloc: the slice partial sums of its force
+// pass (7 rows of FP64 per partial row), for callers that cannot allocate
+// device memory.  Every GPU the library runs on holds one copy until the
+// process ends.  Host code never uses the array's name as an address: it
+// uses the per-device address that scratch_address() looks up.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+constexpr int64_t kScratchRows = (int64_t)(kScratchBytes / (7 * sizeof(double)));
+static __device__ __align__(256) double scratch[kScratchBytes / sizeof(double)];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch[kMaxDevices] = {};
+bool g_scratch_looked_up[kMaxDevices] = {};
+
+// Address of the current device's copy of `scratch` (device `dev`, which
+// must be current), looked up once per device; nullptr if the lookup failed.
+double* scratch_address(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_looked_up[dev]) {
+    g_scratch_looked_up[dev] = true;
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) == hipSuccess)
+      g_scratch[dev] = (double*)ptr;
+    else
+      (void)hipGetLastError();  // do not leave the error for the next launch check
+  }
+  return g_scratch[dev];
+}
 
 constexpr uint32_t kStateMagic = 0x5453424eu;  // "NBST"
 constexpr uint32_t kStateVersion = 2;
@@ -190,6 +221,9 @@ struct nbody_ctx {
   // (eps^2 representable, largest m / eps^3 far from overflow): the lean
   // tile-relative build may run
   bool lean_ok = false;
+  // this device's copy of the static scratch (nbody_force_noalloc), looked
+  // up at init with the context's device current; nullptr if unavailable
+  double* scratch = nullptr;
   Ctl ctl{};
   bool profile = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_pending;  // recorded, not yet read
@@ -378,6 +412,11 @@ nbody_status nbody_init(nbody_ctx** out, int64_t n_total, int32_t n_clusters, co
   c->p = *p;
   c->stream = (hipStream_t)hip_stream;
   c->ws = (unsigned char*)workspace;
+  {
+    int dev = -1;
+    if (hipGetDevice(&dev) == hipSuccess) c->scratch = scratch_address(dev);
+    else (void)hipGetLastError();
+  }
   c->n = n_total;
   c->nc = n_clusters;
   c->coff.assign(cluster_offsets, cluster_offsets + n_clusters + 1);
@@ -541,6 +580,8 @@ nbody_status nbody_predict(nbody_ctx* c, const double* t_pred) {
   return NBODY_OK;
 }
 
+namespace {
+
 // After block steps the predicted state is partial and the corrected
 // particles' entries are from before their correction: predict every
 // particle again to each cluster's time before a direct force or corrector
@@ -553,20 +594,17 @@ nbody_status complete_prediction(nbody_ctx* c) {
   return NBODY_OK;
 }
 
-nbody_status nbody_force(nbody_ctx* c, const int32_t* active_idx, const int64_t* active_offsets, int64_t n_active,
-                         double* acc, double* jerk, double* pot) {
-  if (!c || n_active < 0 || n_active > c->n) return NBODY_E_INVAL;
-  if (n_active == 0) return NBODY_OK;
-  if (!active_idx || !active_offsets || !acc || !jerk) return NBODY_E_INVAL;
-  if (!c->predicted) return NBODY_E_STATE;
-  const DevState& s = c->s;
+// The force pass of nbody_force on the state view `s` (the context's, or
+// one whose partial rows live in the static scratch).
+nbody_status force_pass(nbody_ctx* c, const DevState& s, const int32_t* active_idx, const int64_t* active_offsets,
+                        int64_t n_active, double* acc, double* jerk, double* pot, bool profile) {
   const nbody_status r = complete_prediction(c);
   if (r != NBODY_OK) return r;
   c->sel_valid = false;  // the plan is replaced
   HIP_OK(launch_map_active(s, active_idx, n_active, c->stream));  // particle ids -> slots
   HIP_OK(launch_plan(s, active_offsets, n_active, c->target_items, c->stream));
   std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
-  if (c->profile) {
+  if (profile) {
     if (!c->prof_free.empty()) {
       ev = c->prof_free.back();
       c->prof_free.pop_back();
@@ -578,12 +616,55 @@ nbody_status nbody_force(nbody_ctx* c, const int32_t* active_idx, const int64_t*
   }
   HIP_OK(launch_force(s, force_mode(c), pot != nullptr, c->ctl.near_tau > 0.0, split_only(c), c->lean_ok, s.ulist,
                       c->grid, -1, c->target_items, c->stream));
-  if (c->profile) {
+  if (profile) {
     HIP_OK(hipEventRecord(ev.second, c->stream));
     c->prof_pending.push_back(ev);
   }
   HIP_OK(launch_reduce(s, active_offsets, n_active, acc, jerk, pot, c->stream));
   return NBODY_OK;
+}
+
+}  // namespace
+
+nbody_status nbody_force(nbody_ctx* c, const int32_t* active_idx, const int64_t* active_offsets, int64_t n_active,
+                         double* acc, double* jerk, double* pot) {
+  if (!c || n_active < 0 || n_active > c->n) return NBODY_E_INVAL;
+  if (n_active == 0) return NBODY_OK;
+  if (!active_idx || !active_offsets || !acc || !jerk) return NBODY_E_INVAL;
+  if (!c->predicted) return NBODY_E_STATE;
+  return force_pass(c, c->s, active_idx, active_offsets, n_active, acc, jerk, pot, c->profile);
+}
+
+namespace {
+
+// Most partial rows a force pass over n_active entries can plan.  A cluster
+// with na > 0 entries gets S * na rows, where S <= ceil(target / chunks)
+// (chunks = ceil(na / iwg) i-chunks of at most variant_iwg(0) = 512 entries)
+// and S <= its number of LDS tiles; so S * na < target * 512 + na, and
+// S * na <= na * (tiles of the largest cluster).  Never more than the
+// context's own partial-row capacity.
+int64_t planned_rows_bound(const nbody_ctx* c, int64_t n_active) {
+  int64_t tiles = 1;
+  for (int k = 0; k < c->nc; ++k) tiles = std::max(tiles, (c->coff[k + 1] - c->coff[k] + kTile - 1) / kTile);
+  const int64_t by_target = (int64_t)c->nc * c->target_items * variant_iwg(0) + n_active;
+  const int64_t by_tiles = n_active * tiles;
+  return std::min(c->s.rows_cap, std::min(by_target, by_tiles));
+}
+
+}  // namespace
+
+nbody_status nbody_force_noalloc(nbody_ctx* c, const int32_t* active_idx, const int64_t* active_offsets,
+                                 int64_t n_active, double* acc, double* jerk, double* pot) {
+  if (!c || n_active < 0 || n_active > c->n) return NBODY_E_INVAL;
+  if (n_active == 0) return NBODY_OK;
+  if (!active_idx || !active_offsets || !acc || !jerk) return NBODY_E_INVAL;
+  if (!c->predicted) return NBODY_E_STATE;
+  if (!c->scratch) return NBODY_E_HIP;
+  if (planned_rows_bound(c, n_active) > kScratchRows) return NBODY_E_INVAL;
+  DevState s = c->s;
+  s.part = c->scratch;  // every row a pass reads is written by that pass first: nothing to clear
+  s.rows_cap = kScratchRows;
+  return force_pass(c, s, active_idx, active_offsets, n_active, acc, jerk, pot, false);
 }
 
 nbody_status nbody_correct(nbody_ctx* c, const int32_t* active_idx, const int64_t* active_offsets, int64_t n_active,

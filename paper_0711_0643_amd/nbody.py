@@ -37,6 +37,7 @@ EXPORTED = [
     "nbody_set_params",
     "nbody_predict",
     "nbody_force",
+    "nbody_force_noalloc",
     "nbody_correct",
     "nbody_step",
     "nbody_sync",
@@ -143,6 +144,8 @@ def lib() -> ctypes.CDLL:
         L.nbody_predict.restype = st
         L.nbody_force.argtypes = [p, p, p, i64, p, p, p]
         L.nbody_force.restype = st
+        L.nbody_force_noalloc.argtypes = [p, p, p, i64, p, p, p]
+        L.nbody_force_noalloc.restype = st
         L.nbody_correct.argtypes = [p, p, p, i64, p, p]
         L.nbody_correct.restype = st
         L.nbody_step.argtypes = [p, i32, f64]
@@ -387,6 +390,14 @@ class Sim:
 
     def force(self, active_idx, active_offsets=None, pot: bool = False, out=None):
         """a, k (3, n_act) and phi (n_act,) float64 tensors on the device."""
+        return self._force("nbody_force", active_idx, active_offsets, pot, out)
+
+    def force_noalloc(self, active_idx, active_offsets=None, pot: bool = False, out=None):
+        """As force(), through nbody_force_noalloc (partials in the library's
+        static device scratch)."""
+        return self._force("nbody_force_noalloc", active_idx, active_offsets, pot, out)
+
+    def _force(self, entry, active_idx, active_offsets, pot, out):
         torch = self._torch
         act, aoff = self._active(active_idx, active_offsets)
         na = act.numel()
@@ -396,8 +407,8 @@ class Sim:
             ph = torch.empty((na,), dtype=torch.float64, device=self.device) if pot else None
         else:
             acc, jerk, ph = out
-        _check(lib().nbody_force(self._ctx, act.data_ptr(), aoff.data_ptr(), na, acc.data_ptr(), jerk.data_ptr(),
-                                 ph.data_ptr() if ph is not None else None), "nbody_force")
+        _check(getattr(lib(), entry)(self._ctx, act.data_ptr(), aoff.data_ptr(), na, acc.data_ptr(), jerk.data_ptr(),
+                                     ph.data_ptr() if ph is not None else None), entry)
         self._keep = (act, aoff)  # alive until the stream has consumed them
         return acc, jerk, ph
 
