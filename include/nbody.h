@@ -295,7 +295,13 @@ NBODY_API nbody_status nbody_get_layout(const nbody_ctx *ctx, nbody_layout *out)
  *                 mid_tau * |a_i| (or the jerk analogue above mid_tau * |k_i|)
  *                 is summed again with FP64 position differences (L: the
  *                 i's distance from the tile centre plus the tile's size;
- *                 default 4). */
+ *                 default 4).
+ *   fp64_below: tile-relative format only: a cluster whose block has fewer
+ *                 active particles than this is evaluated with the FP64
+ *                 arithmetic (default 1024; 0: never).  Such passes are bound
+ *                 by latency and per-item work, not by arithmetic, and the
+ *                 FP64 kernel is as fast there or faster, and exact.
+ *   reserved: must be 0. */
 typedef struct {
     int32_t target_items;
     int32_t min_block[4];
@@ -307,6 +313,8 @@ typedef struct {
     int32_t small_min_block[4];
     double near_tau_k;
     double mid_tau;
+    int32_t fp64_below;
+    int32_t reserved;
 } nbody_tuning;
 NBODY_API nbody_status nbody_get_tuning(const nbody_ctx *ctx, nbody_tuning *out);
 NBODY_API nbody_status nbody_set_tuning(nbody_ctx *ctx, const nbody_tuning *t);

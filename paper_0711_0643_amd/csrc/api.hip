@@ -56,6 +56,8 @@ double* scratch_address(int dev) {
 }
 
 constexpr uint32_t kStateMagic = 0x5453424eu;  // "NBST"
+// Default of the tuning field fp64_below.
+constexpr int32_t kDefaultFp64Below = 1024;
 constexpr uint32_t kStateVersion = 2;
 
 struct Layout {
@@ -519,6 +521,7 @@ nbody_status nbody_init(nbody_ctx** out, int64_t n_total, int32_t n_clusters, co
   c->ctl.near_tau = 0.25;
   c->ctl.near_tau_k = 1.0;
   c->ctl.mid_tau = 4.0;
+  c->ctl.fp64_below = kDefaultFp64Below;
 
   const size_t N = (size_t)n_total;
   hipStream_t st = c->stream;
@@ -867,6 +870,8 @@ nbody_status nbody_get_tuning(const nbody_ctx* c, nbody_tuning* t) {
   t->near_tau = c->ctl.near_tau;
   t->near_tau_k = c->ctl.near_tau_k;
   t->mid_tau = c->ctl.mid_tau;
+  t->fp64_below = c->ctl.fp64_below;
+  t->reserved = 0;
   return NBODY_OK;
 }
 
@@ -884,7 +889,7 @@ nbody_status nbody_set_tuning(nbody_ctx* c, const nbody_tuning* t) {
     if (i > 0 && t->min_block[i - 1] < t->min_block[i]) return NBODY_E_INVAL;
     if (i > 0 && t->small_min_block[i - 1] < t->small_min_block[i]) return NBODY_E_INVAL;
   }
-  if (t->small_cluster_n < 0) return NBODY_E_INVAL;
+  if (t->small_cluster_n < 0 || t->fp64_below < 0 || t->reserved != 0) return NBODY_E_INVAL;
   c->target_items = t->target_items;
   c->grid = t->grid;
   c->mixed_mode = t->mixed_format == 2 ? kTR : t->mixed_format == 1 ? kMX64 : kDS;
@@ -893,6 +898,7 @@ nbody_status nbody_set_tuning(nbody_ctx* c, const nbody_tuning* t) {
   c->ctl.near_tau = t->near_tau;
   c->ctl.near_tau_k = t->near_tau_k;
   c->ctl.mid_tau = t->mid_tau;
+  c->ctl.fp64_below = t->fp64_below;
   for (int i = 0; i < kNumVariants - 1; ++i) c->ctl.vmin[i] = t->min_block[i];
   for (int i = 0; i < kNumVariants - 1; ++i) c->ctl.vmin_small[i] = t->small_min_block[i];
   c->ctl.small_n = t->small_cluster_n;

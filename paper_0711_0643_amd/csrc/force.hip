@@ -852,6 +852,20 @@ __device__ void run_item(const DevState& s, const int32_t* __restrict__ act, con
   }
 }
 
+// One work item in the launch's mode, or (tile-relative mode, f64 set) in
+// FP64 arithmetic with the same layout.
+template <int MODE, int JL, int IPT, bool POT, bool NEAR, bool LEAN>
+__device__ __forceinline__ void run_layout(bool f64, const DevState& s, const int32_t* __restrict__ act, const Plan& P,
+                                           int c, int64_t local, unsigned char* lds, float* wmax) {
+  if constexpr (MODE == kTR) {
+    if (f64) {
+      run_item<kF64, JL, IPT, POT, false>(s, act, P, c, local, lds, wmax);
+      return;
+    }
+  }
+  run_item<MODE, JL, IPT, POT, NEAR, LEAN>(s, act, P, c, local, lds, wmax);
+}
+
 // POT: also sum the potential (partial row 6); without it row 6 is not written.
 // NEAR: FP64 evaluation of near pairs in the mixed modes.
 // SPLIT: only the layouts that split j over lanes (2, 3, 4).  They need at
@@ -886,15 +900,19 @@ force_kernel(DevState s, const int32_t* __restrict__ act, int par, int64_t targe
   } else {
     total = s.ctl->total_items;
   }
+  // tile-relative mode: blocks below fp64_below run the FP64 arithmetic
+  // (the predictor has written the FP64 x_p, v_p of every particle)
+  const int32_t fp64_below = MODE == kTR ? s.ctl->fp64_below : 0;
   for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
     const int c = single ? 0 : lds_lookup ? last_at_or_below(offs_sh, s.nc, item) : find_cluster(s.plan, s.nc, item);
     const Plan P = single ? P1 : s.plan[c];
     const int64_t local = item - P.item_off;
+    const bool f64 = P.n_act < fp64_below;  // the same for the whole workgroup
     if constexpr (SPLIT) {
       switch (P.variant) {
-        case 2: run_item<MODE, 4, 1, POT, NEAR>(s, act, P, c, local, lds, wmax); break;
-        case 3: run_item<MODE, 16, 1, POT, NEAR>(s, act, P, c, local, lds, wmax); break;
-        case 4: run_item<MODE, 64, 1, POT, NEAR>(s, act, P, c, local, lds, wmax); break;
+        case 2: run_layout<MODE, 4, 1, POT, NEAR, false>(f64, s, act, P, c, local, lds, wmax); break;
+        case 3: run_layout<MODE, 16, 1, POT, NEAR, false>(f64, s, act, P, c, local, lds, wmax); break;
+        case 4: run_layout<MODE, 64, 1, POT, NEAR, false>(f64, s, act, P, c, local, lds, wmax); break;
         default:
           if (threadIdx.x == 0)
             __hip_atomic_fetch_or(s.status, (int32_t)ST_STATE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -902,11 +920,11 @@ force_kernel(DevState s, const int32_t* __restrict__ act, int par, int64_t targe
       }
     } else {
       switch (P.variant) {
-        case 0: run_item<MODE, 1, 2, POT, NEAR, LEAN>(s, act, P, c, local, lds, wmax); break;
-        case 1: run_item<MODE, 1, 1, POT, NEAR, LEAN>(s, act, P, c, local, lds, wmax); break;
-        case 2: run_item<MODE, 4, 1, POT, NEAR>(s, act, P, c, local, lds, wmax); break;
-        case 3: run_item<MODE, 16, 1, POT, NEAR>(s, act, P, c, local, lds, wmax); break;
-        default: run_item<MODE, 64, 1, POT, NEAR>(s, act, P, c, local, lds, wmax); break;
+        case 0: run_layout<MODE, 1, 2, POT, NEAR, LEAN>(f64, s, act, P, c, local, lds, wmax); break;
+        case 1: run_layout<MODE, 1, 1, POT, NEAR, LEAN>(f64, s, act, P, c, local, lds, wmax); break;
+        case 2: run_layout<MODE, 4, 1, POT, NEAR, false>(f64, s, act, P, c, local, lds, wmax); break;
+        case 3: run_layout<MODE, 16, 1, POT, NEAR, false>(f64, s, act, P, c, local, lds, wmax); break;
+        default: run_layout<MODE, 64, 1, POT, NEAR, false>(f64, s, act, P, c, local, lds, wmax); break;
       }
     }
     __syncthreads();  // LDS is reused by the next item

@@ -109,6 +109,8 @@ class Tuning(ctypes.Structure):
         ("small_min_block", ctypes.c_int32 * 4),
         ("near_tau_k", ctypes.c_double),
         ("mid_tau", ctypes.c_double),
+        ("fp64_below", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 
@@ -339,7 +341,7 @@ class Sim:
                 "mixed_format": t.mixed_format, "rsq_bias_correct": t.rsq_bias_correct,
                 "near_tau": t.near_tau, "small_cluster_n": t.small_cluster_n,
                 "small_min_block": list(t.small_min_block), "near_tau_k": t.near_tau_k,
-                "mid_tau": t.mid_tau}
+                "mid_tau": t.mid_tau, "fp64_below": t.fp64_below}
 
     def set_tuning(self, **kw) -> None:
         cur = self.get_tuning()
@@ -354,6 +356,7 @@ class Sim:
         t.near_tau = float(cur["near_tau"])
         t.near_tau_k = float(cur["near_tau_k"])
         t.mid_tau = float(cur["mid_tau"])
+        t.fp64_below = int(cur["fp64_below"])
         t.small_cluster_n = int(cur["small_cluster_n"])
         for i in range(4):
             t.small_min_block[i] = int(cur["small_min_block"][i])

@@ -32,7 +32,10 @@ pytestmark = pytest.mark.gpu
 def _sim(m, x, v, eps, precision, coff=None, **kw):
     import paper_0711_0643_amd as nb
 
-    return nb.Sim(m, x, v, eps, cluster_offsets=coff, precision=precision, **kw)
+    sim = nb.Sim(m, x, v, eps, cluster_offsets=coff, precision=precision, **kw)
+    if precision == 1:
+        sim.set_tuning(fp64_below=0)  # the mixed arithmetic at every block size
+    return sim
 
 
 def _gpu_force(sim, act, aoff=None, pot=True):
@@ -405,3 +408,54 @@ def test_batch_of_256_clusters_ragged_blocks(precision):
         else:
             _check_mixed(part, ref, oracle.force_abs(m[b:e], x[:, b:e], v[:, b:e], eps[c], loc))
     sim.close()
+
+
+def test_small_blocks_of_the_mixed_mode_run_the_fp64_arithmetic():
+    """With the default fp64_below (1024), a block of fewer active particles
+    is evaluated with the FP64 arithmetic in the tile-relative mixed mode:
+    the same bits as the FP64 precision for every small-block layout, in a
+    single cluster and in a batch where one cluster's block is large."""
+    import torch
+
+    import paper_0711_0643_amd as nb
+
+    n = 20000
+    m, x, v = icgen.plummer(n, 44)
+    eps = 1.0 / n
+    banner("mixed small blocks in FP64")
+    mixed = nb.Sim(m, x, v, eps, precision=1)
+    fp64 = nb.Sim(m, x, v, eps, precision=0)
+    assert mixed.get_tuning()["fp64_below"] == 1024
+    for na in (1, 7, 30, 200, 1023):
+        act = icgen.active_subset(n, na, seed=na)
+        got = mixed.force(act, pot=True)
+        ref = fp64.force(act, pot=True)
+        torch.cuda.synchronize()
+        for u, w in zip(got, ref):
+            assert torch.equal(u, w), na
+    act = icgen.active_subset(n, 1024, seed=3)
+    got = [t.cpu().numpy() for t in mixed.force(act, pot=True)]
+    ref = [t.cpu().numpy() for t in fp64.force(act, pot=True)]
+    assert not np.array_equal(got[0], ref[0])  # the mixed arithmetic from 1024 on
+    assert rel_err(got[0], ref[0]).max() <= 1e-6
+    mixed.close()
+    fp64.close()
+
+    # a batch: cluster 0 with a large block (mixed), clusters 1, 2 small (FP64)
+    m, x, v, coff, eps = icgen.ensemble(3, 17, 3000, 20000)
+    sizes = np.diff(coff)
+    big = int(sizes[0])
+    k0 = min(big, 4096)
+    acts = [int(coff[0]) + np.arange(k0), int(coff[1]) + np.arange(5), int(coff[2]) + np.arange(300)]
+    act = np.concatenate(acts).astype(np.int32)
+    aoff = np.array([0, k0, k0 + 5, k0 + 305], dtype=np.int64)
+    mixed = nb.Sim(m, x, v, eps, cluster_offsets=coff, precision=1)
+    fp64 = nb.Sim(m, x, v, eps, cluster_offsets=coff, precision=0)
+    got = [t.cpu().numpy() for t in mixed.force(act, aoff)[:2]]
+    ref = [t.cpu().numpy() for t in fp64.force(act, aoff)[:2]]
+    for u, w in zip(got, ref):
+        assert np.array_equal(u[:, k0:], w[:, k0:])  # the small blocks: FP64 bits
+    if k0 >= 1024:
+        assert rel_err(got[0][:, :k0], ref[0][:, :k0]).max() <= 1e-6
+    mixed.close()
+    fp64.close()
