@@ -155,9 +155,11 @@ NBODY_API nbody_status nbody_force(nbody_ctx *ctx, const int32_t *active_idx, co
  * Limit: the pass may plan at most 1198372 partial rows (7 FP64 each); a
  * call that could exceed it returns NBODY_E_INVAL and enqueues nothing.  It
  * is accepted whenever n_active * ceil(N_max / 256) <= 1198372 (N_max: the
- * largest cluster) or n_clusters * target_items * 512 + n_active <= 1198372
- * (e.g. any block of a single cluster of up to 65536 particles at the
- * default target_items 2048).
+ * largest cluster) or n_clusters * target_items * C + n_active <= 1198372,
+ * C the largest i-chunk of the layouts the block can reach under min_block
+ * (512 entries with two i per lane, 256 with one, 64, 16, 4 with 4, 16, 64
+ * lanes per i): e.g. any block of a single cluster of up to 65536 particles
+ * at the default tuning (target_items 4096 on 256 CUs, C = 256).
  * Every call on one GPU, from any context, shares that array, and the
  * array keeps the last call's contents: calls that overlap on one GPU (on
  * different streams) race and give wrong results.  NBODY_E_HIP if the
@@ -245,12 +247,12 @@ NBODY_API nbody_status nbody_get_layout(const nbody_ctx *ctx, nbody_layout *out)
  * its own size, its block size and these values (never on other clusters
  * in the batch); changing them changes force sums at rounding level only.
  *   target_items: work items (i-chunk x j-slice) a cluster's force pass is
- *                 split into when it has enough tiles (default: 8 per CU;
- *                 1 .. 16384).
+ *                 split into when it has enough tiles (default: 16 per
+ *                 CU; 1 .. 16384).
  *   min_block: smallest block size that uses, in order, the layouts with
  *              two i per lane, one i per lane, 4 lanes per i and 16 lanes
- *              per i (default 1024, 1024, 48, 12: the one-lane-per-i layout
- *              is off by default); smaller blocks use 64
+ *              per i (default 2^30, 1024, 48, 12: the two-i-per-lane
+ *              layout is off by default); smaller blocks use 64
  *              lanes per i.  Must be non-increasing and >= 1.
  *   small_cluster_n, small_min_block: clusters of fewer than
  *              small_cluster_n particles use small_min_block instead of
@@ -262,7 +264,7 @@ NBODY_API nbody_status nbody_get_layout(const nbody_ctx *ctx, nbody_layout *out)
  *              entry), the force pass runs a kernel build with only the
  *              j-split layouts, at higher occupancy; results per layout
  *              are the same bits either way.
- *   grid: persistent workgroups of the force launch (default: 8 per CU).
+ *   grid: persistent workgroups of the force launch (default: 16 per CU).
  *   mixed_format: how the mixed kernel forms the FP32 pair difference
  *                 x_j - x_i: 0 from double-single FP32 pairs
  *                 (hi_j - hi_i) + (lo_j - lo_i); 1 in FP64 from the FP64
@@ -301,6 +303,12 @@ NBODY_API nbody_status nbody_get_layout(const nbody_ctx *ctx, nbody_layout *out)
  *                 arithmetic (default 1024; 0: never).  Such passes are bound
  *                 by latency and per-item work, not by arithmetic, and the
  *                 FP64 kernel is as fast there or faster, and exact.
+ *   window, waves: build of the tile-relative kernel with the near test on
+ *                 the lean path (every cluster softened) and no potential:
+ *                 FP32 window of 16, 32 or 64 pairs and an occupancy of 2,
+ *                 3 or 4 waves per SIMD (default 32 and 4; results change
+ *                 at rounding level with the window).  Other passes use
+ *                 their own fixed build.
  *   reserved: must be 0. */
 typedef struct {
     int32_t target_items;
@@ -314,6 +322,8 @@ typedef struct {
     double near_tau_k;
     double mid_tau;
     int32_t fp64_below;
+    int32_t window;
+    int32_t waves;
     int32_t reserved;
 } nbody_tuning;
 NBODY_API nbody_status nbody_get_tuning(const nbody_ctx *ctx, nbody_tuning *out);

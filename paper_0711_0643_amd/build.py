@@ -10,7 +10,8 @@ PKG = Path(__file__).resolve().parent
 ROOT = PKG.parent
 CSRC = PKG / "csrc"
 LIB = PKG / "libnbody.so"
-SOURCES = ["force.hip", "step.hip", "api.hip"]
+SOURCES = ["force.hip", "force_tuned.hip", "step.hip", "api.hip"]
+BUILD = PKG / "_build"
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",
@@ -32,18 +33,33 @@ def hipcc() -> str:
     return "hipcc"
 
 
-def build(verbose: bool = False) -> Path:
-    """Compile every source for gfx950 into paper_0711_0643_amd/libnbody.so."""
-    tmp = LIB.with_suffix(".so.tmp")
-    cmd = [hipcc(), *HIPCC_FLAGS, f"-I{ROOT / 'include'}", f"-I{CSRC}", "-o", str(tmp)]
-    cmd += [str(CSRC / s) for s in SOURCES]
+def _run(cmd) -> str:
     r = subprocess.run(cmd, capture_output=True, text=True)
     noise = "is not a recognized feature for this target"
     err = "\n".join(l for l in r.stderr.splitlines() if noise not in l)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed ({r.returncode}):\n{err}")
-    if verbose and err.strip():
-        print(err, file=sys.stderr)
+    return err
+
+
+def build(verbose: bool = False) -> Path:
+    """Compile every source for gfx950 (one hipcc per source, in parallel)
+    and link them into paper_0711_0643_amd/libnbody.so."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    BUILD.mkdir(exist_ok=True)
+    compile_flags = [f for f in HIPCC_FLAGS if f != "-shared"]
+    objs = [BUILD / (s + ".o") for s in SOURCES]
+    cmds = [[hipcc(), *compile_flags, f"-I{ROOT / 'include'}", f"-I{CSRC}", "-c", "-o", str(o), str(CSRC / s)]
+            for s, o in zip(SOURCES, objs)]
+    with ThreadPoolExecutor(max_workers=len(cmds)) as pool:
+        errs = list(pool.map(_run, cmds))
+    tmp = LIB.with_suffix(".so.tmp")
+    errs.append(_run([hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", str(tmp), *map(str, objs)]))
+    if verbose:
+        for e in errs:
+            if e.strip():
+                print(e, file=sys.stderr)
     os.replace(tmp, LIB)
     return LIB
 

@@ -195,9 +195,11 @@ struct nbody_ctx {
   int64_t n = 0;
   int32_t nc = 0;
   int32_t nch = 0;
-  int grid = 2048;        // persistent force grid
-  int target_items = 2048;  // work items a force pass aims at per cluster
+  int grid = 4096;        // persistent force grid
+  int target_items = 4096;  // work items a force pass aims at per cluster
   int mixed_mode = kTR;   // position format of the mixed kernel
+  int kwindow = 32;       // FP32 window of the lean tile-relative kernel (16, 32, 64)
+  int kwaves = 4;         // its occupancy, waves per SIMD (2, 3, 4)
   int rsq_correct = 1;    // remove the mean bias of v_rsq_f32 in the mixed kernel
   hipGraph_t graph[2] = {nullptr, nullptr};
   hipGraphExec_t gexec[2] = {nullptr, nullptr};  // one block step, of parity 0 and 1
@@ -319,8 +321,7 @@ hipError_t capture_steps(nbody_ctx* c, int steps, int par0, hipGraph_t* g) {
     e = launch_select(s, c->target_items, mode, par, c->cap_stream);
     if (e == hipSuccess)
       e = launch_force(s, mode, c->p.compute_pot != 0, c->ctl.near_tau > 0.0, split_only(c), c->lean_ok, s.act,
-                       c->grid, par,
-                       c->target_items, c->cap_stream);
+                       c->grid, par, c->target_items, c->cap_stream, c->kwindow, c->kwaves);
     if (e == hipSuccess) e = launch_reduce_correct_step(s, c->p.compute_pot != 0, par, c->target_items, c->cap_stream);
   }
   *g = nullptr;
@@ -447,8 +448,8 @@ nbody_status nbody_init(nbody_ctx** out, int64_t n_total, int32_t n_clusters, co
 
   int dev = 0, cus = 256;
   if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  c->grid = cus * 8;
-  c->target_items = cus * 8;
+  c->grid = cus * 16;
+  c->target_items = cus * 16;
 
   // host-side tables: cluster of each particle, selection chunks
   std::vector<int32_t> cid((size_t)n_total), cl_ch((size_t)n_clusters + 1);
@@ -509,7 +510,7 @@ nbody_status nbody_init(nbody_ctx** out, int64_t n_total, int32_t n_clusters, co
   s.fout = (double*)(w + L.fout);
   s.status = (int32_t*)(w + L.status);
 
-  c->ctl.vmin[0] = 1024;
+  c->ctl.vmin[0] = 1 << 30;  // two i per lane: off (one i per lane is faster on gfx950)
   c->ctl.vmin[1] = 1024;
   c->ctl.vmin[2] = 48;
   c->ctl.vmin[3] = 12;
@@ -618,7 +619,7 @@ nbody_status force_pass(nbody_ctx* c, const DevState& s, const int32_t* active_i
     HIP_OK(hipEventRecord(ev.first, c->stream));
   }
   HIP_OK(launch_force(s, force_mode(c), pot != nullptr, c->ctl.near_tau > 0.0, split_only(c), c->lean_ok, s.ulist,
-                      c->grid, -1, c->target_items, c->stream));
+                      c->grid, -1, c->target_items, c->stream, c->kwindow, c->kwaves));
   if (profile) {
     HIP_OK(hipEventRecord(ev.second, c->stream));
     c->prof_pending.push_back(ev);
@@ -642,14 +643,23 @@ namespace {
 
 // Most partial rows a force pass over n_active entries can plan.  A cluster
 // with na > 0 entries gets S * na rows, where S <= ceil(target / chunks)
-// (chunks = ceil(na / iwg) i-chunks of at most variant_iwg(0) = 512 entries)
-// and S <= its number of LDS tiles; so S * na < target * 512 + na, and
-// S * na <= na * (tiles of the largest cluster).  Never more than the
+// (chunks = ceil(na / iwg) i-chunks of iwg entries, iwg that of the layout
+// the plan picks) and S <= its number of LDS tiles; so S * na < target *
+// iwg + na, and S * na <= na * (tiles of the largest cluster).  iwg is
+// bounded by the largest i-chunk of the layouts a block of at most n_active
+// entries can reach under the current thresholds.  Never more than the
 // context's own partial-row capacity.
 int64_t planned_rows_bound(const nbody_ctx* c, int64_t n_active) {
-  int64_t tiles = 1;
-  for (int k = 0; k < c->nc; ++k) tiles = std::max(tiles, (c->coff[k + 1] - c->coff[k] + kTile - 1) / kTile);
-  const int64_t by_target = (int64_t)c->nc * c->target_items * variant_iwg(0) + n_active;
+  int64_t tiles = 1, iwg = variant_iwg(kNumVariants - 1);
+  for (int k = 0; k < c->nc; ++k) {
+    const int64_t nn = c->coff[k + 1] - c->coff[k];
+    tiles = std::max(tiles, (nn + kTile - 1) / kTile);
+    for (int v = 0; v < kNumVariants - 1; ++v) {
+      const int64_t thr = nn < c->ctl.small_n ? c->ctl.vmin_small[v] : c->ctl.vmin[v];
+      if (thr <= std::min(n_active, nn)) iwg = std::max(iwg, (int64_t)variant_iwg(v));
+    }
+  }
+  const int64_t by_target = (int64_t)c->nc * c->target_items * iwg + n_active;
   const int64_t by_tiles = n_active * tiles;
   return std::min(c->s.rows_cap, std::min(by_target, by_tiles));
 }
@@ -871,6 +881,8 @@ nbody_status nbody_get_tuning(const nbody_ctx* c, nbody_tuning* t) {
   t->near_tau_k = c->ctl.near_tau_k;
   t->mid_tau = c->ctl.mid_tau;
   t->fp64_below = c->ctl.fp64_below;
+  t->window = c->kwindow;
+  t->waves = c->kwaves;
   t->reserved = 0;
   return NBODY_OK;
 }
@@ -890,6 +902,7 @@ nbody_status nbody_set_tuning(nbody_ctx* c, const nbody_tuning* t) {
     if (i > 0 && t->small_min_block[i - 1] < t->small_min_block[i]) return NBODY_E_INVAL;
   }
   if (t->small_cluster_n < 0 || t->fp64_below < 0 || t->reserved != 0) return NBODY_E_INVAL;
+  if ((t->window != 16 && t->window != 32 && t->window != 64) || t->waves < 2 || t->waves > 4) return NBODY_E_INVAL;
   c->target_items = t->target_items;
   c->grid = t->grid;
   c->mixed_mode = t->mixed_format == 2 ? kTR : t->mixed_format == 1 ? kMX64 : kDS;
@@ -899,6 +912,8 @@ nbody_status nbody_set_tuning(nbody_ctx* c, const nbody_tuning* t) {
   c->ctl.near_tau_k = t->near_tau_k;
   c->ctl.mid_tau = t->mid_tau;
   c->ctl.fp64_below = t->fp64_below;
+  c->kwindow = t->window;
+  c->kwaves = t->waves;
   for (int i = 0; i < kNumVariants - 1; ++i) c->ctl.vmin[i] = t->min_block[i];
   for (int i = 0; i < kNumVariants - 1; ++i) c->ctl.vmin_small[i] = t->small_min_block[i];
   c->ctl.small_n = t->small_cluster_n;

@@ -20,24 +20,39 @@ def test_tuner_picks_a_parity_passing_config(precision, tmp_path, monkeypatch):
     from paper_0711_0643_amd import tune
 
     monkeypatch.setenv("NBODY_TUNE_CACHE", str(tmp_path / "tune.json"))
-    n = 4096
+    n = 16384
     m, x, v = icgen.plummer(n, 17)
     eps = 1.0 / n
     banner(f"tune N={n} precision={precision}")
     sim = nb.Sim(m, x, v, eps, precision=precision)
-    cfg = tune.tune(sim, ladder=[1, 64, 1024, n])
+    cfg = tune.tune(sim, ladder=[1, 64, 1024, 4096, n])
     assert cfg == sim.get_tuning()
     data = json.loads((tmp_path / "tune.json").read_text())
     key = tune.cache_key(sim)
     assert key in data and data[key]["tuning"] == cfg
     assert any(r["ok"] for r in data[key]["records"])
-    # the chosen configuration against the oracle on several block sizes
+    # the chosen configuration against the oracle on several block sizes:
+    # acceleration and potential per particle, jerk per particle where its
+    # terms do not cancel by more than a factor 10
     for na in (1, 100, n):
         act = icgen.active_subset(n, na)
         a, k, _ = sim.force(act)
+        _, _, phi = sim.force(act, pot=True)
         torch.cuda.synchronize()
-        ra, rk, _ = oracle.force(m, x, v, eps, act)
-        assert rel_err(a.cpu().numpy(), ra).max() <= (1e-6 if precision == 1 else 1e-12)
+        ra, rk, rphi = oracle.force(m, x, v, eps, act)
+        tol = 1e-6 if precision == 1 else 1e-12
+        assert rel_err(a.cpu().numpy(), ra).max() <= tol
+        assert rel_err(phi.cpu().numpy(), rphi).max() <= tol
+        kappa = oracle.force_abs(m, x, v, eps, act)[1] / np.linalg.norm(rk, axis=0)
+        ek = rel_err(k.cpu().numpy(), rk)
+        assert ek[kappa <= 10].max() <= tol
+    recs = data[key]["records"]
+    assert all({"err", "err_jerk_p999", "err_pot", "ok"} <= set(r) for r in recs)
+    if precision == 1:
+        assert any("fp64_below" in r for r in recs)  # the FP64-arithmetic threshold was searched
+        if cfg["fp64_below"] <= n:  # the full block runs the mixed arithmetic: its builds were searched
+            assert {(r["window"], r["waves"]) for r in recs if "window" in r} == {
+                (w, q) for w in (16, 32, 64) for q in (2, 3, 4)}
     # a second call is served from the cache
     sim2 = nb.Sim(m, x, v, eps, precision=precision)
     assert tune.tune(sim2) == cfg
@@ -81,4 +96,32 @@ def test_batch_tuner_restores_state_and_passes_parity(tmp_path, monkeypatch):
     vs = sim.vp.cpu().numpy()[:, b:e]
     ra, _, _ = oracle.force(m[b:e], xs, vs, eps[0])
     assert rel_err(a.cpu().numpy(), ra).max() <= 1e-6
+    sim.close()
+
+
+@pytest.mark.parametrize("window", [16, 32, 64])
+def test_every_kernel_build_matches_oracle(window):
+    """Each build of the lean tile-relative kernel the tuner may choose
+    (FP32 window 16, 32, 64; 2, 3, 4 waves per SIMD) against the oracle:
+    acceleration per particle, jerk per particle where kappa_k <= 10."""
+    import torch
+
+    import paper_0711_0643_amd as nb
+
+    n = 6000
+    m, x, v = icgen.plummer(n, 23)
+    eps = 1.0 / n
+    sim = nb.Sim(m, x, v, eps, precision=1)
+    for na in (n, 2000):
+        act = icgen.active_subset(n, na, seed=5)
+        ra, rk, _ = oracle.force(m, x, v, eps, act)
+        kappa = oracle.force_abs(m, x, v, eps, act)[1] / np.linalg.norm(rk, axis=0)
+        for waves in (2, 3, 4):
+            banner(f"kernel build window={window} waves={waves} n_act={na}")
+            sim.set_tuning(window=window, waves=waves, small_cluster_n=0, fp64_below=0)
+            a, k, _ = sim.force(act)
+            torch.cuda.synchronize()
+            assert sim.status() == 0
+            assert rel_err(a.cpu().numpy(), ra).max() <= 1e-6
+            assert rel_err(k.cpu().numpy(), rk)[kappa <= 10].max() <= 1e-6
     sim.close()
