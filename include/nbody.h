@@ -305,8 +305,8 @@ NBODY_API nbody_status nbody_get_layout(const nbody_ctx *ctx, nbody_layout *out)
  *                 FP64 kernel is as fast there or faster, and exact.
  *   window, waves: build of the tile-relative kernel with the near test on
  *                 the lean path (every cluster softened) and no potential:
- *                 FP32 window of 16, 32 or 64 pairs and an occupancy of 2,
- *                 3 or 4 waves per SIMD (default 32 and 4; results change
+ *                 FP32 window of 16, 32 or 64 pairs and an occupancy of 2
+ *                 to 5 waves per SIMD (default 32 and 5; results change
  *                 at rounding level with the window).  Other passes use
  *                 their own fixed build.
  *   reserved: must be 0. */

@@ -199,7 +199,7 @@ struct nbody_ctx {
   int target_items = 4096;  // work items a force pass aims at per cluster
   int mixed_mode = kTR;   // position format of the mixed kernel
   int kwindow = 32;       // FP32 window of the lean tile-relative kernel (16, 32, 64)
-  int kwaves = 4;         // its occupancy, waves per SIMD (2, 3, 4)
+  int kwaves = 5;         // its occupancy, waves per SIMD (2 to 5)
   int rsq_correct = 1;    // remove the mean bias of v_rsq_f32 in the mixed kernel
   hipGraph_t graph[2] = {nullptr, nullptr};
   hipGraphExec_t gexec[2] = {nullptr, nullptr};  // one block step, of parity 0 and 1
@@ -902,7 +902,7 @@ nbody_status nbody_set_tuning(nbody_ctx* c, const nbody_tuning* t) {
     if (i > 0 && t->small_min_block[i - 1] < t->small_min_block[i]) return NBODY_E_INVAL;
   }
   if (t->small_cluster_n < 0 || t->fp64_below < 0 || t->reserved != 0) return NBODY_E_INVAL;
-  if ((t->window != 16 && t->window != 32 && t->window != 64) || t->waves < 2 || t->waves > 4) return NBODY_E_INVAL;
+  if ((t->window != 16 && t->window != 32 && t->window != 64) || t->waves < 2 || t->waves > 5) return NBODY_E_INVAL;
   c->target_items = t->target_items;
   c->grid = t->grid;
   c->mixed_mode = t->mixed_format == 2 ? kTR : t->mixed_format == 1 ? kMX64 : kDS;

@@ -6,7 +6,7 @@
 namespace nb {
 
 // WPE: waves per SIMD the kernel is built for (SPLIT: 4, else 3; the lean
-// tile-relative kernel: 4).
+// tile-relative kernel: 5).
 template <int MODE, bool NEAR, bool SPLIT, bool LEAN = false, int WPE = (SPLIT ? 4 : 3)>
 static void launch_mode(const ForceLaunch& L, bool pot) {
   if (pot)
@@ -31,8 +31,8 @@ static hipError_t launch_family(const ForceLaunch& L, int mode, bool pot, bool n
       break;
     case kTR:
       if (near && L.lean && !SPLIT) {
-        if (!pot && (L.window != 32 || L.waves != 4)) return launch_force_tuned(L);
-        launch_mode<kTR, true, false, true, 4>(L, pot);
+        if (!pot && (L.window != 32 || L.waves != 5)) return launch_force_tuned(L);
+        launch_mode<kTR, true, false, true, 5>(L, pot);
       }
       else if (near) launch_mode<kTR, true, SPLIT>(L, pot);
       else launch_mode<kTR, false, SPLIT>(L, pot);

@@ -950,8 +950,8 @@ struct ForceLaunch {
 };
 
 // The lean tile-relative kernel without the potential in one of the
-// autotuner's other builds (window 16, 32 or 64; 2, 3 or 4 waves per SIMD;
-// not the default 32 / 4): force_tuned.hip.
+// autotuner's other builds (window 16, 32 or 64; 2 to 5 waves per SIMD;
+// not the default 32 / 5): force_tuned.hip.
 hipError_t launch_force_tuned(const ForceLaunch& L);
 
 }  // namespace nb

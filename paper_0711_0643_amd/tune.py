@@ -9,7 +9,7 @@ What is searched (all runtime knobs of the library):
   * (mixed) the block size below which the tile-relative kernel runs the
     FP64 arithmetic (fp64_below), from the same ladder;
   * (mixed) the build of the lean tile-relative kernel: FP32 window of 16,
-    32 or 64 pairs and 2, 3 or 4 waves per SIMD (window, waves), on the full
+    32 or 64 pairs and 2 to 5 waves per SIMD (window, waves), on the full
     block;
   * the j-slicing target (target_items) and the persistent grid size (grid)
     for the full block;
@@ -231,7 +231,7 @@ def tune(sim, use_cache: bool = True, ladder=None, verbose: bool = False) -> dic
     best = None
     if prec == 1 and base["mixed_format"] == 2 and n >= tuned.get("fp64_below", 0):
         for window in (16, 32, 64):
-            for waves in (2, 3, 4):
+            for waves in (2, 3, 4, 5):
                 cfg = dict(tuned, window=window, waves=waves)
                 ms = trial(cfg, act, aoff, ref, n_act=n, window=window, waves=waves)
                 if best is None or ms < best[0]:

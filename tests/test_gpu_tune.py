@@ -52,7 +52,7 @@ def test_tuner_picks_a_parity_passing_config(precision, tmp_path, monkeypatch):
         assert any("fp64_below" in r for r in recs)  # the FP64-arithmetic threshold was searched
         if cfg["fp64_below"] <= n:  # the full block runs the mixed arithmetic: its builds were searched
             assert {(r["window"], r["waves"]) for r in recs if "window" in r} == {
-                (w, q) for w in (16, 32, 64) for q in (2, 3, 4)}
+                (w, q) for w in (16, 32, 64) for q in (2, 3, 4, 5)}
     # a second call is served from the cache
     sim2 = nb.Sim(m, x, v, eps, precision=precision)
     assert tune.tune(sim2) == cfg
@@ -102,7 +102,7 @@ def test_batch_tuner_restores_state_and_passes_parity(tmp_path, monkeypatch):
 @pytest.mark.parametrize("window", [16, 32, 64])
 def test_every_kernel_build_matches_oracle(window):
     """Each build of the lean tile-relative kernel the tuner may choose
-    (FP32 window 16, 32, 64; 2, 3, 4 waves per SIMD) against the oracle:
+    (FP32 window 16, 32, 64; 2 to 5 waves per SIMD) against the oracle:
     acceleration per particle, jerk per particle where kappa_k <= 10."""
     import torch
 
@@ -116,7 +116,7 @@ def test_every_kernel_build_matches_oracle(window):
         act = icgen.active_subset(n, na, seed=5)
         ra, rk, _ = oracle.force(m, x, v, eps, act)
         kappa = oracle.force_abs(m, x, v, eps, act)[1] / np.linalg.norm(rk, axis=0)
-        for waves in (2, 3, 4):
+        for waves in (2, 3, 4, 5):
             banner(f"kernel build window={window} waves={waves} n_act={na}")
             sim.set_tuning(window=window, waves=waves, small_cluster_n=0, fp64_below=0)
             a, k, _ = sim.force(act)
