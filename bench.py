@@ -57,6 +57,8 @@ def parse():
                     help="full-block runs only (no n_act sweep, no alternative kernels): clean profiles")
     ap.add_argument("--workload", choices=["c1", "c2", "c3", "c4", "c5", "model"], default=None,
                     help="instead of the headline line, run one of the integration workloads and print its record")
+    ap.add_argument("--profile-window", action="store_true",
+                    help="open the rocprofv3 --selected-regions window around the timed force launches only")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run 5 plain device copies of 256 MiB (reference for HBM byte counters)")
     return ap.parse_args()
@@ -106,6 +108,26 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+PROFILE_WINDOW = False
+_roctx = None
+
+
+def profile_window(open_: bool) -> None:
+    """With --profile-window: open (resume) or close (pause) the region a
+    profiler started with rocprofv3 --selected-regions records, so that its
+    kernel statistics cover exactly the timed launches."""
+    global _roctx
+    if not PROFILE_WINDOW:
+        return
+    import ctypes
+
+    if _roctx is None:
+        lib = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "lib", "librocprofiler-sdk-roctx.so")
+        _roctx = ctypes.CDLL(lib)
+    fn = _roctx.roctxProfilerResume if open_ else _roctx.roctxProfilerPause
+    fn(ctypes.c_uint64(0))
+
+
 def time_steps(sim, steps, warmup, dt):
     import torch
 
@@ -140,10 +162,12 @@ def kernel_time(sim, act, aoff, reps, warm=3):
     sim.profile_force(True)
     sim.profile_read()
     times = []
+    profile_window(True)
     for _ in range(reps):
         sim.force(act, aoff, out=(acc, jerk, None))
         ms, launches = sim.profile_read()
         times.append(ms / launches)
+    profile_window(False)
     sim.profile_force(False)
     sim.sync()
     return float(np.median(times)) / 1e3, acc, jerk
@@ -434,7 +458,9 @@ def integration_evidence():
 
 
 def main():
+    global PROFILE_WINDOW
     args = parse()
+    PROFILE_WINDOW = args.profile_window
     if args.calibrate_copy:
         calibrate_copy()
         return
