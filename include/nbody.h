@@ -252,7 +252,9 @@ NBODY_API nbody_status nbody_get_layout(const nbody_ctx *ctx, nbody_layout *out)
  *   min_block: smallest block size that uses, in order, the layouts with
  *              two i per lane, one i per lane, 4 lanes per i and 16 lanes
  *              per i (default 2^30, 1024, 48, 12: the two-i-per-lane
- *              layout is off by default); smaller blocks use 64
+ *              layout is off by default, and the tile-relative format never
+ *              uses it: min_block[0] and small_min_block[0] are ignored
+ *              there); smaller blocks use 64
  *              lanes per i.  Must be non-increasing and >= 1.
  *   small_cluster_n, small_min_block: clusters of fewer than
  *              small_cluster_n particles use small_min_block instead of
@@ -298,18 +300,18 @@ NBODY_API nbody_status nbody_get_layout(const nbody_ctx *ctx, nbody_layout *out)
  *                 is summed again with FP64 position differences (L: the
  *                 i's distance from the tile centre plus the tile's size;
  *                 default 4).
- *   fp64_below: tile-relative format only: a cluster whose block has fewer
- *                 active particles than this is evaluated with the FP64
- *                 arithmetic (default 1024; 0: never).  Such passes are bound
- *                 by latency and per-item work, not by arithmetic, and the
- *                 FP64 kernel is as fast there or faster, and exact.
  *   window, waves: build of the tile-relative kernel with the near test on
  *                 the lean path (every cluster softened) and no potential:
  *                 FP32 window of 16, 32 or 64 pairs and an occupancy of 2
- *                 to 5 waves per SIMD (default 32 and 5; results change
+ *                 to 5 waves per SIMD (default 32 and 3, the build that
+ *                 needs no scratch memory; results change
  *                 at rounding level with the window).  Other passes use
  *                 their own fixed build.
- *   reserved: must be 0. */
+ *   reserved: must be 0.
+ * In the tile-relative format the mixed arithmetic runs in the
+ * one-lane-per-i layout (blocks from min_block[1] on); the layouts that
+ * split j over lanes (small blocks, latency-bound) run the FP64 arithmetic,
+ * which is as fast there and exact. */
 typedef struct {
     int32_t target_items;
     int32_t min_block[4];
@@ -321,10 +323,9 @@ typedef struct {
     int32_t small_min_block[4];
     double near_tau_k;
     double mid_tau;
-    int32_t fp64_below;
     int32_t window;
     int32_t waves;
-    int32_t reserved;
+    int32_t reserved[2];
 } nbody_tuning;
 NBODY_API nbody_status nbody_get_tuning(const nbody_ctx *ctx, nbody_tuning *out);
 NBODY_API nbody_status nbody_set_tuning(nbody_ctx *ctx, const nbody_tuning *t);

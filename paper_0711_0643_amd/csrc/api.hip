@@ -56,8 +56,6 @@ double* scratch_address(int dev) {
 }
 
 constexpr uint32_t kStateMagic = 0x5453424eu;  // "NBST"
-// Default of the tuning field fp64_below.
-constexpr int32_t kDefaultFp64Below = 1024;
 constexpr uint32_t kStateVersion = 2;
 
 struct Layout {
@@ -199,7 +197,7 @@ struct nbody_ctx {
   int target_items = 4096;  // work items a force pass aims at per cluster
   int mixed_mode = kTR;   // position format of the mixed kernel
   int kwindow = 32;       // FP32 window of the lean tile-relative kernel (16, 32, 64)
-  int kwaves = 5;         // its occupancy, waves per SIMD (2 to 5)
+  int kwaves = 3;         // its occupancy, waves per SIMD (2 to 5)
   int rsq_correct = 1;    // remove the mean bias of v_rsq_f32 in the mixed kernel
   hipGraph_t graph[2] = {nullptr, nullptr};
   hipGraphExec_t gexec[2] = {nullptr, nullptr};  // one block step, of parity 0 and 1
@@ -249,9 +247,12 @@ nbody_status upload_ctl(nbody_ctx* c) {
   c->ctl.dt_max = c->p.dt_max;
   c->ctl.dt_min = c->p.dt_min;
   c->ctl.compute_pot = c->p.compute_pot ? 1 : 0;
+  // the tile-relative format has no two-i-per-lane build: plan without it
+  Ctl up = c->ctl;
+  if (force_mode(c) == kTR) up.vmin[0] = up.vmin_small[0] = 1 << 30;
   // host-owned fields only: the rsq_* fields at the end are written on the device
-  HIP_OK(hipMemcpyAsync(c->ws + c->L.ctl, &c->ctl, offsetof(Ctl, rsq_scale3), hipMemcpyHostToDevice, c->stream));
-  HIP_OK(hipStreamSynchronize(c->stream));  // c->ctl is host memory the copy reads
+  HIP_OK(hipMemcpyAsync(c->ws + c->L.ctl, &up, offsetof(Ctl, rsq_scale3), hipMemcpyHostToDevice, c->stream));
+  HIP_OK(hipStreamSynchronize(c->stream));  // `up` is host memory the copy reads
   return NBODY_OK;
 }
 
@@ -522,7 +523,6 @@ nbody_status nbody_init(nbody_ctx** out, int64_t n_total, int32_t n_clusters, co
   c->ctl.near_tau = 0.25;
   c->ctl.near_tau_k = 1.0;
   c->ctl.mid_tau = 4.0;
-  c->ctl.fp64_below = kDefaultFp64Below;
 
   const size_t N = (size_t)n_total;
   hipStream_t st = c->stream;
@@ -880,10 +880,9 @@ nbody_status nbody_get_tuning(const nbody_ctx* c, nbody_tuning* t) {
   t->near_tau = c->ctl.near_tau;
   t->near_tau_k = c->ctl.near_tau_k;
   t->mid_tau = c->ctl.mid_tau;
-  t->fp64_below = c->ctl.fp64_below;
   t->window = c->kwindow;
   t->waves = c->kwaves;
-  t->reserved = 0;
+  t->reserved[0] = t->reserved[1] = 0;
   return NBODY_OK;
 }
 
@@ -901,7 +900,7 @@ nbody_status nbody_set_tuning(nbody_ctx* c, const nbody_tuning* t) {
     if (i > 0 && t->min_block[i - 1] < t->min_block[i]) return NBODY_E_INVAL;
     if (i > 0 && t->small_min_block[i - 1] < t->small_min_block[i]) return NBODY_E_INVAL;
   }
-  if (t->small_cluster_n < 0 || t->fp64_below < 0 || t->reserved != 0) return NBODY_E_INVAL;
+  if (t->small_cluster_n < 0 || t->reserved[0] != 0 || t->reserved[1] != 0) return NBODY_E_INVAL;
   if ((t->window != 16 && t->window != 32 && t->window != 64) || t->waves < 2 || t->waves > 5) return NBODY_E_INVAL;
   c->target_items = t->target_items;
   c->grid = t->grid;
@@ -911,7 +910,6 @@ nbody_status nbody_set_tuning(nbody_ctx* c, const nbody_tuning* t) {
   c->ctl.near_tau = t->near_tau;
   c->ctl.near_tau_k = t->near_tau_k;
   c->ctl.mid_tau = t->mid_tau;
-  c->ctl.fp64_below = t->fp64_below;
   c->kwindow = t->window;
   c->kwaves = t->waves;
   for (int i = 0; i < kNumVariants - 1; ++i) c->ctl.vmin[i] = t->min_block[i];

@@ -79,10 +79,7 @@ struct Ctl {
   double t_end;
   double eta, eta_init, dt_max, dt_min;
   int32_t compute_pot;
-  // tile-relative mixed mode: a cluster whose block has fewer active
-  // particles than this runs the FP64 arithmetic (its pass is bound by
-  // latency and per-item work, where FP64 is as fast and exact)
-  int32_t fp64_below;
+  int32_t pad;
   int64_t total_items;  // items of the current plan
   int64_t total_rows;   // partial rows of the current plan
   int64_t total_red;    // reduce work units of the current plan

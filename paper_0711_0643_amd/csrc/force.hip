@@ -5,8 +5,9 @@
 
 namespace nb {
 
-// WPE: waves per SIMD the kernel is built for (SPLIT: 4, else 3; the lean
-// tile-relative kernel: 5).
+// WPE: waves per SIMD the kernel is built for (SPLIT: 4, else 3).  Every
+// default build needs no scratch memory: a kernel that does costs several
+// microseconds more per launch, which dominates the small blocks.
 template <int MODE, bool NEAR, bool SPLIT, bool LEAN = false, int WPE = (SPLIT ? 4 : 3)>
 static void launch_mode(const ForceLaunch& L, bool pot) {
   if (pot)
@@ -30,12 +31,17 @@ static hipError_t launch_family(const ForceLaunch& L, int mode, bool pot, bool n
       else launch_mode<kMX64, false, SPLIT>(L, pot);
       break;
     case kTR:
-      if (near && L.lean && !SPLIT) {
-        if (!pot && (L.window != 32 || L.waves != 5)) return launch_force_tuned(L);
-        launch_mode<kTR, true, false, true, 5>(L, pot);
+      if (SPLIT) {
+        // every split layout runs the FP64 arithmetic in this mode
+        launch_mode<kF64, false, true>(L, pot);
+      } else if (near && L.lean) {
+        if (!pot && (L.window != 32 || L.waves != 3)) return launch_force_tuned(L);
+        launch_mode<kTR, true, false, true, 3>(L, pot);
+      } else if (near) {
+        launch_mode<kTR, true, false>(L, pot);
+      } else {
+        launch_mode<kTR, false, false>(L, pot);
       }
-      else if (near) launch_mode<kTR, true, SPLIT>(L, pot);
-      else launch_mode<kTR, false, SPLIT>(L, pot);
       break;
     default: return hipErrorInvalidValue;
   }

@@ -855,20 +855,6 @@ __device__ void run_item(const DevState& s, const int32_t* __restrict__ act, con
   }
 }
 
-// One work item in the launch's mode, or (tile-relative mode, f64 set) in
-// FP64 arithmetic with the same layout.
-template <int MODE, int JL, int IPT, bool POT, bool NEAR, bool LEAN, int FW>
-__device__ __forceinline__ void run_layout(bool f64, const DevState& s, const int32_t* __restrict__ act, const Plan& P,
-                                           int c, int64_t local, unsigned char* lds, float* wmax) {
-  if constexpr (MODE == kTR) {
-    if (f64) {
-      run_item<kF64, JL, IPT, POT, false>(s, act, P, c, local, lds, wmax);
-      return;
-    }
-  }
-  run_item<MODE, JL, IPT, POT, NEAR, LEAN, FW>(s, act, P, c, local, lds, wmax);
-}
-
 // POT: also sum the potential (partial row 6); without it row 6 is not written.
 // NEAR: FP64 evaluation of near pairs in the mixed modes.
 // SPLIT: only the layouts that split j over lanes (2, 3, 4).  They need at
@@ -908,19 +894,19 @@ force_kernel(DevState s, const int32_t* __restrict__ act, int par, int64_t targe
   } else {
     total = s.ctl->total_items;
   }
-  // tile-relative mode: blocks below fp64_below run the FP64 arithmetic
-  // (the predictor has written the FP64 x_p, v_p of every particle)
-  const int32_t fp64_below = MODE == kTR ? s.ctl->fp64_below : 0;
+  // the tile-relative mode runs the FP64 arithmetic in the layouts that
+  // split j over lanes (SM: the split-layout mode)
+  constexpr int SM = MODE == kTR ? kF64 : MODE;
+  constexpr bool SNEAR = NEAR && SM != kF64;
   for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
     const int c = single ? 0 : lds_lookup ? last_at_or_below(offs_sh, s.nc, item) : find_cluster(s.plan, s.nc, item);
     const Plan P = single ? P1 : s.plan[c];
     const int64_t local = item - P.item_off;
-    const bool f64 = P.n_act < fp64_below;  // the same for the whole workgroup
     if constexpr (SPLIT) {
       switch (P.variant) {
-        case 2: run_layout<MODE, 4, 1, POT, NEAR, false, FW>(f64, s, act, P, c, local, lds, wmax); break;
-        case 3: run_layout<MODE, 16, 1, POT, NEAR, false, FW>(f64, s, act, P, c, local, lds, wmax); break;
-        case 4: run_layout<MODE, 64, 1, POT, NEAR, false, FW>(f64, s, act, P, c, local, lds, wmax); break;
+        case 2: run_item<SM, 4, 1, POT, SNEAR, false, FW>(s, act, P, c, local, lds, wmax); break;
+        case 3: run_item<SM, 16, 1, POT, SNEAR, false, FW>(s, act, P, c, local, lds, wmax); break;
+        case 4: run_item<SM, 64, 1, POT, SNEAR, false, FW>(s, act, P, c, local, lds, wmax); break;
         default:
           if (threadIdx.x == 0)
             __hip_atomic_fetch_or(s.status, (int32_t)ST_STATE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -928,11 +914,21 @@ force_kernel(DevState s, const int32_t* __restrict__ act, int par, int64_t targe
       }
     } else {
       switch (P.variant) {
-        case 0: run_layout<MODE, 1, 2, POT, NEAR, LEAN, FW>(f64, s, act, P, c, local, lds, wmax); break;
-        case 1: run_layout<MODE, 1, 1, POT, NEAR, LEAN, FW>(f64, s, act, P, c, local, lds, wmax); break;
-        case 2: run_layout<MODE, 4, 1, POT, NEAR, false, FW>(f64, s, act, P, c, local, lds, wmax); break;
-        case 3: run_layout<MODE, 16, 1, POT, NEAR, false, FW>(f64, s, act, P, c, local, lds, wmax); break;
-        default: run_layout<MODE, 64, 1, POT, NEAR, false, FW>(f64, s, act, P, c, local, lds, wmax); break;
+        case 0:
+          if constexpr (MODE == kTR) {
+            // the tile-relative format has no two-i-per-lane build (its
+            // registers spill, and a kernel that needs scratch memory costs
+            // microseconds per launch); the host plans without that layout
+            if (threadIdx.x == 0)
+              __hip_atomic_fetch_or(s.status, (int32_t)ST_STATE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          } else {
+            run_item<MODE, 1, 2, POT, NEAR, LEAN, FW>(s, act, P, c, local, lds, wmax);
+          }
+          break;
+        case 1: run_item<MODE, 1, 1, POT, NEAR, LEAN, FW>(s, act, P, c, local, lds, wmax); break;
+        case 2: run_item<SM, 4, 1, POT, SNEAR, false, FW>(s, act, P, c, local, lds, wmax); break;
+        case 3: run_item<SM, 16, 1, POT, SNEAR, false, FW>(s, act, P, c, local, lds, wmax); break;
+        default: run_item<SM, 64, 1, POT, SNEAR, false, FW>(s, act, P, c, local, lds, wmax); break;
       }
     }
     __syncthreads();  // LDS is reused by the next item
@@ -951,7 +947,7 @@ struct ForceLaunch {
 
 // The lean tile-relative kernel without the potential in one of the
 // autotuner's other builds (window 16, 32 or 64; 2 to 5 waves per SIMD;
-// not the default 32 / 5): force_tuned.hip.
+// not the default 32 / 3): force_tuned.hip.
 hipError_t launch_force_tuned(const ForceLaunch& L);
 
 }  // namespace nb

@@ -108,15 +108,20 @@ __device__ __forceinline__ void tile_frame(const DevState& s, int ch, bool have,
     red[tid >> 6][12] = mm;
   }
   __syncthreads();
+  // 13 threads combine the wave results of one quantity each, in parallel
+  if (tid < 13) {
+    double r = red[0][tid];
+    for (int w = 1; w < kSelThreads / 64; ++w) r = tid < 6 ? fmin(r, red[w][tid]) : fmax(r, red[w][tid]);
+    red[0][tid] = r;
+  }
+  __syncthreads();
   if (tid == 0) {
-    for (int w = 1; w < kSelThreads / 64; ++w) {
 #pragma unroll
-      for (int d = 0; d < 6; ++d) {
-        lo[d] = fmin(lo[d], red[w][d]);
-        hi[d] = fmax(hi[d], red[w][6 + d]);
-      }
-      mm = fmax(mm, red[w][12]);
+    for (int d = 0; d < 6; ++d) {
+      lo[d] = red[0][d];
+      hi[d] = red[0][6 + d];
     }
+    mm = red[0][12];
     double* f = s.tmeta + (int64_t)ch * kTileMeta;
     double w2 = 0.0, d2 = 0.0;
 #pragma unroll
@@ -824,6 +829,15 @@ __global__ void __launch_bounds__(kSelThreads) select_init_kernel(DevState s, in
   }
 }
 
+// Whether a block of cluster c can reach the one-lane-per-i layout under
+// the current thresholds (the cluster is at least as large as that layout's
+// smallest block).
+__device__ __forceinline__ bool tr_layout_reachable(const DevState& s, int c) {
+  const int64_t nn = s.coff[c + 1] - s.coff[c];
+  const int64_t thr = nn < s.ctl->small_n ? s.ctl->vmin_small[1] : s.ctl->vmin[1];
+  return nn >= thr;
+}
+
 __global__ void __launch_bounds__(kSelThreads) select_kernel(DevState s, int mode, int par, int64_t target_items) {
   static_assert(kSelChunk == kSelThreads, "one particle per thread");
   __shared__ double buf[kSelThreads / 64];
@@ -878,8 +892,11 @@ __global__ void __launch_bounds__(kSelThreads) select_kernel(DevState s, int mod
   double xo[3] = {0.0, 0.0, 0.0}, vo[3] = {0.0, 0.0, 0.0};
   if (have && advancing) predict_from(s, i, ahead ? pin : load_pred(s, i), tsys, mode, member, xo, vo);
   // the mixed force pass reads the tile frame of every chunk of an
-  // advancing cluster (the condition is the same for the whole workgroup)
-  if (advancing && mode != kF64) tile_frame(s, ch, have, xo, vo, have ? s.m[i] : 0.0);
+  // advancing cluster (the condition is the same for the whole workgroup);
+  // the tile-relative mode only in clusters large enough for its
+  // one-lane-per-i layout (its split layouts run the FP64 arithmetic)
+  if (advancing && mode != kF64 && (mode != kTR || tr_layout_reachable(s, c)))
+    tile_frame(s, ch, have, xo, vo, have ? s.m[i] : 0.0);
 
   // members, and the smallest t + dt of the others
   const double rest = block_min(member ? INFINITY : tt, buf);

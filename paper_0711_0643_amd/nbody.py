@@ -109,10 +109,9 @@ class Tuning(ctypes.Structure):
         ("small_min_block", ctypes.c_int32 * 4),
         ("near_tau_k", ctypes.c_double),
         ("mid_tau", ctypes.c_double),
-        ("fp64_below", ctypes.c_int32),
         ("window", ctypes.c_int32),
         ("waves", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 2),
     ]
 
 
@@ -343,7 +342,7 @@ class Sim:
                 "mixed_format": t.mixed_format, "rsq_bias_correct": t.rsq_bias_correct,
                 "near_tau": t.near_tau, "small_cluster_n": t.small_cluster_n,
                 "small_min_block": list(t.small_min_block), "near_tau_k": t.near_tau_k,
-                "mid_tau": t.mid_tau, "fp64_below": t.fp64_below, "window": t.window, "waves": t.waves}
+                "mid_tau": t.mid_tau, "window": t.window, "waves": t.waves}
 
     def set_tuning(self, **kw) -> None:
         cur = self.get_tuning()
@@ -358,7 +357,6 @@ class Sim:
         t.near_tau = float(cur["near_tau"])
         t.near_tau_k = float(cur["near_tau_k"])
         t.mid_tau = float(cur["mid_tau"])
-        t.fp64_below = int(cur["fp64_below"])
         t.window = int(cur["window"])
         t.waves = int(cur["waves"])
         t.small_cluster_n = int(cur["small_cluster_n"])

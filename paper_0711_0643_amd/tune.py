@@ -6,11 +6,10 @@ What is searched (all runtime knobs of the library):
     with 2 i per lane, 1 i per lane, 4, 16 lanes per i (min_block, applied
     to every cluster: small_cluster_n = 0), chosen by timing every layout at
     a ladder of block sizes;
-  * (mixed) the block size below which the tile-relative kernel runs the
-    FP64 arithmetic (fp64_below), from the same ladder;
   * (mixed) the build of the lean tile-relative kernel: FP32 window of 16,
     32 or 64 pairs and 2 to 5 waves per SIMD (window, waves), on the full
-    block;
+    block, among the builds no slower than the default on the smallest
+    block (a build that spills registers costs microseconds per launch);
   * the j-slicing target (target_items) and the persistent grid size (grid)
     for the full block;
   * the position format of the mixed kernel (mixed_format).
@@ -185,7 +184,6 @@ def tune(sim, use_cache: bool = True, ladder=None, verbose: bool = False) -> dic
     ladder = ladder or sorted({1, 4, 16, 64, 256, 1024, 4096, n} & set(range(1, n + 1)))
     records = []
     best_variant = {}
-    tr_wins = {}
     for na in ladder:
         act, aoff = active(na)
         ref = reference(act, aoff)
@@ -193,18 +191,10 @@ def tune(sim, use_cache: bool = True, ladder=None, verbose: bool = False) -> dic
         for v in range(5):
             # min_block forcing layout v for every block size (non-increasing)
             cfg = dict(base, min_block=[BIG if i < v else 1 for i in range(4)], small_cluster_n=0)
-            if prec == 1:
-                cfg["fp64_below"] = 0  # the layouts in the mixed arithmetic
             ms = trial(cfg, act, aoff, ref, n_act=na, variant=v)
             if ms < float("inf"):
                 times[v] = ms
         best_variant[na] = min(times, key=times.get) if times else 1
-        if prec == 1 and base["mixed_format"] == 2:
-            # the same best layout in the FP64 arithmetic
-            v = best_variant[na]
-            cfg = dict(base, min_block=[BIG if i < v else 1 for i in range(4)], small_cluster_n=0, fp64_below=BIG)
-            ms64 = trial(cfg, act, aoff, ref, n_act=na, variant=v, fp64_below=BIG)
-            tr_wins[na] = times.get(v, float("inf")) <= ms64
     # thresholds: variant v is used from the smallest ladder size where a
     # variant <= v wins onwards (monotone by construction)
     min_block = []
@@ -214,29 +204,34 @@ def tune(sim, use_cache: bool = True, ladder=None, verbose: bool = False) -> dic
     for i in range(1, 4):
         min_block[i] = min(min_block[i], min_block[i - 1])
     tuned = dict(base, min_block=min_block, small_cluster_n=0)
-    if tr_wins:
-        # FP64 arithmetic below the smallest ladder size from which the
-        # mixed arithmetic wins at every larger size
-        fp64_below = BIG
-        for na in sorted(tr_wins, reverse=True):
-            if not tr_wins[na]:
-                break
-            fp64_below = na
-        tuned["fp64_below"] = min(fp64_below, n + 1)
 
     # full block: kernel build (mixed), slicing target, grid and mixed format
     act, aoff = active(n)
     ref = reference(act, aoff)
     cus = torch.cuda.get_device_properties(dev).multi_processor_count
     best = None
-    if prec == 1 and base["mixed_format"] == 2 and n >= tuned.get("fp64_below", 0):
+    if prec == 1 and base["mixed_format"] == 2 and min(min_block[0], min_block[1]) <= n:
+        # the full block runs a one-lane-per-i layout: the kernel build matters.
+        # A build must also be no slower than the default one on the smallest
+        # block of the ladder: builds that spill registers need scratch
+        # memory, which costs microseconds per launch at every block size.
+        small_act, small_aoff = active(ladder[0])
+        small_ref = reference(small_act, small_aoff)
+        t_small = {}
+        for window in (16, 32, 64):
+            for waves in (2, 3, 4, 5):
+                cfg = dict(tuned, window=window, waves=waves)
+                t_small[(window, waves)] = trial(cfg, small_act, small_aoff, small_ref, n_act=ladder[0],
+                                                 window=window, waves=waves)
+        limit = 1.05 * t_small[(base["window"], base["waves"])]
         for window in (16, 32, 64):
             for waves in (2, 3, 4, 5):
                 cfg = dict(tuned, window=window, waves=waves)
                 ms = trial(cfg, act, aoff, ref, n_act=n, window=window, waves=waves)
-                if best is None or ms < best[0]:
+                if t_small[(window, waves)] <= limit and (best is None or ms < best[0]):
                     best = (ms, cfg)
-        tuned = best[1]
+        if best is not None:
+            tuned = best[1]
     best = None
     formats = (0, 1, 2) if prec == 1 else (base["mixed_format"],)
     for fmt in formats:

@@ -34,7 +34,9 @@ def _sim(m, x, v, eps, precision, coff=None, **kw):
 
     sim = nb.Sim(m, x, v, eps, cluster_offsets=coff, precision=precision, **kw)
     if precision == 1:
-        sim.set_tuning(fp64_below=0)  # the mixed arithmetic at every block size
+        # every block in the one-lane-per-i layout, the one that runs the
+        # tile-relative arithmetic (the split layouts run the FP64 one)
+        sim.set_tuning(min_block=[1 << 30, 1, 1, 1], small_cluster_n=0)
     return sim
 
 
@@ -410,11 +412,11 @@ def test_batch_of_256_clusters_ragged_blocks(precision):
     sim.close()
 
 
-def test_small_blocks_of_the_mixed_mode_run_the_fp64_arithmetic():
-    """With the default fp64_below (1024), a block of fewer active particles
-    is evaluated with the FP64 arithmetic in the tile-relative mixed mode:
-    the same bits as the FP64 precision for every small-block layout, in a
-    single cluster and in a batch where one cluster's block is large."""
+def test_split_layouts_of_the_mixed_mode_run_the_fp64_arithmetic():
+    """In the tile-relative format the layouts that split j over lanes
+    (blocks below min_block[1], 1024 by default) run the FP64 arithmetic:
+    the same bits as the FP64 precision, in a single cluster and in a batch
+    beside a cluster whose block runs the mixed arithmetic."""
     import torch
 
     import paper_0711_0643_amd as nb
@@ -425,7 +427,7 @@ def test_small_blocks_of_the_mixed_mode_run_the_fp64_arithmetic():
     banner("mixed small blocks in FP64")
     mixed = nb.Sim(m, x, v, eps, precision=1)
     fp64 = nb.Sim(m, x, v, eps, precision=0)
-    assert mixed.get_tuning()["fp64_below"] == 1024
+    assert mixed.get_tuning()["min_block"][1] == 1024
     for na in (1, 7, 30, 200, 1023):
         act = icgen.active_subset(n, na, seed=na)
         got = mixed.force(act, pot=True)
@@ -441,21 +443,23 @@ def test_small_blocks_of_the_mixed_mode_run_the_fp64_arithmetic():
     mixed.close()
     fp64.close()
 
-    # a batch: cluster 0 with a large block (mixed), clusters 1, 2 small (FP64)
-    m, x, v, coff, eps = icgen.ensemble(3, 17, 3000, 20000)
-    sizes = np.diff(coff)
-    big = int(sizes[0])
-    k0 = min(big, 4096)
-    acts = [int(coff[0]) + np.arange(k0), int(coff[1]) + np.arange(5), int(coff[2]) + np.arange(300)]
-    act = np.concatenate(acts).astype(np.int32)
-    aoff = np.array([0, k0, k0 + 5, k0 + 305], dtype=np.int64)
+    # a batch: a cluster of 20000 with a block of 4096 (mixed arithmetic)
+    # beside clusters of 300 and 900 with small blocks (FP64 arithmetic)
+    parts = [icgen.plummer(k, 50 + k) for k in (20000, 300, 900)]
+    m = np.concatenate([p[0] for p in parts])
+    x = np.concatenate([p[1] for p in parts], axis=1)
+    v = np.concatenate([p[2] for p in parts], axis=1)
+    coff = np.array([0, 20000, 20300, 21200], dtype=np.int64)
+    eps = np.array([1.0 / 20000, 1.0 / 300, 1.0 / 900])
+    act = np.concatenate([np.arange(4096), 20000 + np.arange(5), 20300 + np.arange(300)]).astype(np.int32)
+    aoff = np.array([0, 4096, 4101, 4401], dtype=np.int64)
     mixed = nb.Sim(m, x, v, eps, cluster_offsets=coff, precision=1)
     fp64 = nb.Sim(m, x, v, eps, cluster_offsets=coff, precision=0)
     got = [t.cpu().numpy() for t in mixed.force(act, aoff)[:2]]
     ref = [t.cpu().numpy() for t in fp64.force(act, aoff)[:2]]
     for u, w in zip(got, ref):
-        assert np.array_equal(u[:, k0:], w[:, k0:])  # the small blocks: FP64 bits
-    if k0 >= 1024:
-        assert rel_err(got[0][:, :k0], ref[0][:, :k0]).max() <= 1e-6
+        assert np.array_equal(u[:, 4096:], w[:, 4096:])  # the small blocks: FP64 bits
+    assert not np.array_equal(got[0][:, :4096], ref[0][:, :4096])
+    assert rel_err(got[0][:, :4096], ref[0][:, :4096]).max() <= 1e-6
     mixed.close()
     fp64.close()

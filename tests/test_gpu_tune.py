@@ -49,8 +49,7 @@ def test_tuner_picks_a_parity_passing_config(precision, tmp_path, monkeypatch):
     recs = data[key]["records"]
     assert all({"err", "err_jerk_p999", "err_pot", "ok"} <= set(r) for r in recs)
     if precision == 1:
-        assert any("fp64_below" in r for r in recs)  # the FP64-arithmetic threshold was searched
-        if cfg["fp64_below"] <= n:  # the full block runs the mixed arithmetic: its builds were searched
+        if min(cfg["min_block"][:2]) <= n:  # the full block runs a one-lane-per-i layout: builds searched
             assert {(r["window"], r["waves"]) for r in recs if "window" in r} == {
                 (w, q) for w in (16, 32, 64) for q in (2, 3, 4, 5)}
     # a second call is served from the cache
@@ -118,7 +117,7 @@ def test_every_kernel_build_matches_oracle(window):
         kappa = oracle.force_abs(m, x, v, eps, act)[1] / np.linalg.norm(rk, axis=0)
         for waves in (2, 3, 4, 5):
             banner(f"kernel build window={window} waves={waves} n_act={na}")
-            sim.set_tuning(window=window, waves=waves, small_cluster_n=0, fp64_below=0)
+            sim.set_tuning(window=window, waves=waves, small_cluster_n=0)
             a, k, _ = sim.force(act)
             torch.cuda.synchronize()
             assert sim.status() == 0
