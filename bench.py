@@ -585,8 +585,8 @@ def main():
             "unit": "TFLOP/s",
             "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
             "traffic": recorded_traffic(),
-            "kernel": "nb::force_kernel<3, false, true, false, true, 32, 3> (mixed tile-relative, no potential, "
-                      "near pairs, lean; FP32 window 32, 3 waves per SIMD)",
+            "kernel": "nb::force_kernel<3, false, true, false, true, 32, 4> (mixed tile-relative, no potential, "
+                      "near pairs, lean; FP32 window 32, 4 waves per SIMD)",
             "flops_per_interaction": FLOPS_ACC_JERK,
             "flop_count_rule": "algorithmic acc + jerk without the potential (FMA = 2, rsqrt = 1); 42 with it",
             "interactions_per_launch": inter_step,

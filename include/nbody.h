@@ -303,7 +303,7 @@ NBODY_API nbody_status nbody_get_layout(const nbody_ctx *ctx, nbody_layout *out)
  *   window, waves: build of the tile-relative kernel with the near test on
  *                 the lean path (every cluster softened) and no potential:
  *                 FP32 window of 16, 32 or 64 pairs and an occupancy of 2
- *                 to 5 waves per SIMD (default 32 and 3, the build that
+ *                 to 5 waves per SIMD (default 32 and 4, the build that
  *                 needs no scratch memory; results change
  *                 at rounding level with the window).  Other passes use
  *                 their own fixed build.

@@ -197,7 +197,7 @@ struct nbody_ctx {
   int target_items = 4096;  // work items a force pass aims at per cluster
   int mixed_mode = kTR;   // position format of the mixed kernel
   int kwindow = 32;       // FP32 window of the lean tile-relative kernel (16, 32, 64)
-  int kwaves = 3;         // its occupancy, waves per SIMD (2 to 5)
+  int kwaves = 4;         // its occupancy, waves per SIMD (2 to 5)
   int rsq_correct = 1;    // remove the mean bias of v_rsq_f32 in the mixed kernel
   hipGraph_t graph[2] = {nullptr, nullptr};
   hipGraphExec_t gexec[2] = {nullptr, nullptr};  // one block step, of parity 0 and 1
@@ -249,7 +249,7 @@ nbody_status upload_ctl(nbody_ctx* c) {
   c->ctl.compute_pot = c->p.compute_pot ? 1 : 0;
   // the tile-relative format has no two-i-per-lane build: plan without it
   Ctl up = c->ctl;
-  if (force_mode(c) == kTR) up.vmin[0] = up.vmin_small[0] = 1 << 30;
+  if (force_mode(c) == kTR) up.vmin[0] = up.vmin_small[0] = INT32_MAX;  // above any block (<= 2^30)
   // host-owned fields only: the rsq_* fields at the end are written on the device
   HIP_OK(hipMemcpyAsync(c->ws + c->L.ctl, &up, offsetof(Ctl, rsq_scale3), hipMemcpyHostToDevice, c->stream));
   HIP_OK(hipStreamSynchronize(c->stream));  // `up` is host memory the copy reads

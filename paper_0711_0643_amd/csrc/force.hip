@@ -35,8 +35,15 @@ static hipError_t launch_family(const ForceLaunch& L, int mode, bool pot, bool n
         // every split layout runs the FP64 arithmetic in this mode
         launch_mode<kF64, false, true>(L, pot);
       } else if (near && L.lean) {
-        if (!pot && (L.window != 32 || L.waves != 3)) return launch_force_tuned(L);
-        launch_mode<kTR, true, false, true, 3>(L, pot);
+        // the default builds that need no scratch memory: 4 waves per SIMD
+        // without the potential, 3 with it
+        if (!pot && (L.window != 32 || L.waves != 4)) return launch_force_tuned(L);
+        if (pot)
+          hipLaunchKernelGGL((force_kernel<kTR, true, true, false, true, 32, 3>), dim3(L.grid), dim3(kForceThreads), 0,
+                             L.st, L.s, L.act, L.par, L.target_items);
+        else
+          hipLaunchKernelGGL((force_kernel<kTR, false, true, false, true, 32, 4>), dim3(L.grid), dim3(kForceThreads), 0,
+                             L.st, L.s, L.act, L.par, L.target_items);
       } else if (near) {
         launch_mode<kTR, true, false>(L, pot);
       } else {

@@ -912,19 +912,20 @@ force_kernel(DevState s, const int32_t* __restrict__ act, int par, int64_t targe
             __hip_atomic_fetch_or(s.status, (int32_t)ST_STATE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           break;
       }
+    } else if constexpr (MODE == kTR) {
+      // the tile-relative format has no two-i-per-lane build (its registers
+      // spill, and a kernel that needs scratch memory costs microseconds
+      // per launch): the host plans it with that layout's threshold above
+      // any block size, so layout 0 never occurs here
+      switch (P.variant) {
+        case 1: run_item<MODE, 1, 1, POT, NEAR, LEAN, FW>(s, act, P, c, local, lds, wmax); break;
+        case 2: run_item<SM, 4, 1, POT, SNEAR, false, FW>(s, act, P, c, local, lds, wmax); break;
+        case 3: run_item<SM, 16, 1, POT, SNEAR, false, FW>(s, act, P, c, local, lds, wmax); break;
+        default: run_item<SM, 64, 1, POT, SNEAR, false, FW>(s, act, P, c, local, lds, wmax); break;
+      }
     } else {
       switch (P.variant) {
-        case 0:
-          if constexpr (MODE == kTR) {
-            // the tile-relative format has no two-i-per-lane build (its
-            // registers spill, and a kernel that needs scratch memory costs
-            // microseconds per launch); the host plans without that layout
-            if (threadIdx.x == 0)
-              __hip_atomic_fetch_or(s.status, (int32_t)ST_STATE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          } else {
-            run_item<MODE, 1, 2, POT, NEAR, LEAN, FW>(s, act, P, c, local, lds, wmax);
-          }
-          break;
+        case 0: run_item<MODE, 1, 2, POT, NEAR, LEAN, FW>(s, act, P, c, local, lds, wmax); break;
         case 1: run_item<MODE, 1, 1, POT, NEAR, LEAN, FW>(s, act, P, c, local, lds, wmax); break;
         case 2: run_item<SM, 4, 1, POT, SNEAR, false, FW>(s, act, P, c, local, lds, wmax); break;
         case 3: run_item<SM, 16, 1, POT, SNEAR, false, FW>(s, act, P, c, local, lds, wmax); break;
@@ -947,7 +948,7 @@ struct ForceLaunch {
 
 // The lean tile-relative kernel without the potential in one of the
 // autotuner's other builds (window 16, 32 or 64; 2 to 5 waves per SIMD;
-// not the default 32 / 3): force_tuned.hip.
+// not the default 32 / 4): force_tuned.hip.
 hipError_t launch_force_tuned(const ForceLaunch& L);
 
 }  // namespace nb

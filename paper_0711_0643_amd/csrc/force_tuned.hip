@@ -1,6 +1,6 @@
 // The autotuner's other builds of the lean tile-relative force kernel
 // without the potential: FP32 window of 16, 32 or 64 pairs and an
-// occupancy of 2 to 5 waves per SIMD (the default, 32 and 3, is built
+// occupancy of 2 to 5 waves per SIMD (the default, 32 and 4, is built
 // with the other kernels in force.hip).  Compiled on its own so that the
 // library's sources build in parallel.
 #include "force_impl.h"
@@ -19,7 +19,7 @@ hipError_t launch_force_tuned(const ForceLaunch& L) {
     case 163: launch_tr<16, 3>(L); break;
     case 164: launch_tr<16, 4>(L); break;
     case 322: launch_tr<32, 2>(L); break;
-    case 324: launch_tr<32, 4>(L); break;
+    case 323: launch_tr<32, 3>(L); break;
     case 642: launch_tr<64, 2>(L); break;
     case 643: launch_tr<64, 3>(L); break;
     case 644: launch_tr<64, 4>(L); break;

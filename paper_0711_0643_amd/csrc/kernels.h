@@ -26,7 +26,7 @@ constexpr int kSelThreads = 256;
 // tile-relative kernel without the potential; other kernels use 32 and
 // their own occupancy.
 hipError_t launch_force(const DevState& s, int mode, bool pot, bool near, bool split, bool lean, const int32_t* act,
-                        int grid, int par, int64_t target_items, hipStream_t st, int window = 32, int waves = 3);
+                        int grid, int par, int64_t target_items, hipStream_t st, int window = 32, int waves = 4);
 
 // Plan the force pass for the active offsets `aoff` (device, nc+1) of an
 // active list of at most n_act_bound entries.  target_items: work items aimed
