@@ -515,7 +515,10 @@ def main():
         elif full:
             sweep = {}
             for na in (1, 64, 1024, 16384, n):
-                sub = torch.as_tensor(icgen.active_subset(n, na, seed=7), device=sim.device)
+                # a random subset of the slots, listed in storage order (the
+                # order in which the block selection lists its members)
+                slots = np.sort(np.random.Generator(np.random.PCG64(7)).permutation(n)[:na])
+                sub = torch.as_tensor(order[slots].astype(np.int32), device=sim.device)
                 soff = torch.tensor([0, na], dtype=torch.int64, device=sim.device)
                 kts, _, _ = kernel_time(sim, sub, soff, 5)
                 ct = call_time(sim, sub, soff, 5)
