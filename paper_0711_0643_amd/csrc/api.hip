@@ -61,7 +61,7 @@ constexpr uint32_t kStateVersion = 2;
 struct Layout {
   size_t coff, eps, cid, ch_cluster, ch_begin, cl_ch, order, slot_of, tmeta, ulist;
   size_t m, x, v, a, k, t, dt, xp, vp, pot, jr;
-  size_t tpred, tnow, inter, steps, cm2, acount, umin, act, aoff, plan, offs, ctl, part, fout, status, eout;
+  size_t tpred, tnow, inter, steps, cm2, cm2n, acount, umin, ucnt, act, aoff, plan, offs, ctl, part, fout, status, eout;
   size_t total;
   int64_t rows_cap;
   int64_t nch_max;
@@ -106,8 +106,10 @@ Layout make_layout(int64_t n, int32_t nc) {
   L.inter = take(8 * C);
   L.steps = take(8 * C);
   L.cm2 = take(16 * (size_t)L.nch_max);
+  L.cm2n = take(8 * (size_t)L.nch_max);
   L.acount = take(8 * C);  // two halves of int32 counters, by step parity
   L.umin = take(8 * N);
+  L.ucnt = take(4 * N);
   L.act = take(4 * N);
   L.aoff = take(8 * (C + 1));
   L.plan = take(sizeof(Plan) * C);
@@ -265,15 +267,16 @@ nbody_status status_from_bits(int32_t bits) {
 }
 
 // Whether no cluster can reach a one-lane-per-i layout: a block holds at
-// most all of its cluster, so a cluster below the threshold of layout 1 (the
+// most all of its cluster and at most the n_active entries of the active
+// list, so a cluster whose bound is below the threshold of layout 1 (the
 // lower of the two; thresholds do not increase with the layout index) never
 // uses layouts 0 or 1.  Then the force pass runs the kernel with only the
 // j-split layouts, which has the higher occupancy.
-bool split_only(const nbody_ctx* c) {
+bool split_only(const nbody_ctx* c, int64_t n_active) {
   for (int k = 0; k < c->nc; ++k) {
     const int64_t nk = c->coff[k + 1] - c->coff[k];
     const int64_t thr = nk < c->ctl.small_n ? c->ctl.vmin_small[1] : c->ctl.vmin[1];
-    if (nk >= thr) return false;
+    if (std::min(nk, n_active) >= thr) return false;
   }
   return true;
 }
@@ -283,8 +286,8 @@ nbody_status force_all_internal(nbody_ctx* c, int mode) {
   const DevState& s = c->s;
   HIP_OK(launch_identity(s, c->stream));
   HIP_OK(launch_plan(s, s.aoff, s.n, c->target_items, c->stream));
-  HIP_OK(launch_force(s, mode, true, c->ctl.near_tau > 0.0, split_only(c), c->lean_ok, s.act, c->grid, -1, c->target_items,
-                      c->stream));
+  HIP_OK(launch_force(s, mode, true, c->ctl.near_tau > 0.0, split_only(c, s.n), c->lean_ok, s.act, c->grid, -1,
+                      c->target_items, c->stream));
   HIP_OK(launch_reduce(s, s.aoff, s.n, s.fout, s.fout + 3 * s.n, s.fout + 6 * s.n, c->stream));
   return NBODY_OK;
 }
@@ -315,15 +318,20 @@ constexpr int kStepsPerGraph = 32;
 hipError_t capture_steps(nbody_ctx* c, int steps, int par0, hipGraph_t* g) {
   const DevState& s = c->s;
   const int mode = force_mode(c);
+  // block sizes are counted where they decide the tile frames: the
+  // tile-relative format with some cluster that can reach its
+  // one-lane-per-i layout
+  const bool counting = mode == kTR && !split_only(c, s.n);
   hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed);
   if (e != hipSuccess) return e;
   for (int k = 0; k < steps && e == hipSuccess; ++k) {
     const int par = (par0 + k) & 1;
-    e = launch_select(s, c->target_items, mode, par, c->cap_stream);
+    e = launch_select(s, c->target_items, mode, par, counting, c->cap_stream);
     if (e == hipSuccess)
-      e = launch_force(s, mode, c->p.compute_pot != 0, c->ctl.near_tau > 0.0, split_only(c), c->lean_ok, s.act,
+      e = launch_force(s, mode, c->p.compute_pot != 0, c->ctl.near_tau > 0.0, split_only(c, s.n), c->lean_ok, s.act,
                        c->grid, par, c->target_items, c->cap_stream, c->kwindow, c->kwaves);
-    if (e == hipSuccess) e = launch_reduce_correct_step(s, c->p.compute_pot != 0, par, c->target_items, c->cap_stream);
+    if (e == hipSuccess)
+      e = launch_reduce_correct_step(s, c->p.compute_pot != 0, par, c->target_items, counting, c->cap_stream);
   }
   *g = nullptr;
   const hipError_t e2 = hipStreamEndCapture(c->cap_stream, g);
@@ -499,8 +507,10 @@ nbody_status nbody_init(nbody_ctx** out, int64_t n_total, int32_t n_clusters, co
   s.inter = (double*)(w + L.inter);
   s.steps = (int64_t*)(w + L.steps);
   s.cm2 = (double*)(w + L.cm2);
+  s.cm2n = (int32_t*)(w + L.cm2n);
   s.acount = (int32_t*)(w + L.acount);
   s.umin = (double*)(w + L.umin);
+  s.ucnt = (int32_t*)(w + L.ucnt);
   s.act = (int32_t*)(w + L.act);
   s.aoff = (int64_t*)(w + L.aoff);
   s.plan = (Plan*)(w + L.plan);
@@ -618,7 +628,8 @@ nbody_status force_pass(nbody_ctx* c, const DevState& s, const int32_t* active_i
     }
     HIP_OK(hipEventRecord(ev.first, c->stream));
   }
-  HIP_OK(launch_force(s, force_mode(c), pot != nullptr, c->ctl.near_tau > 0.0, split_only(c), c->lean_ok, s.ulist,
+  HIP_OK(launch_force(s, force_mode(c), pot != nullptr, c->ctl.near_tau > 0.0, split_only(c, n_active), c->lean_ok,
+                      s.ulist,
                       c->grid, -1, c->target_items, c->stream, c->kwindow, c->kwaves));
   if (profile) {
     HIP_OK(hipEventRecord(ev.second, c->stream));

@@ -55,9 +55,10 @@ enum : int { JR_HX = 0, JR_HY, JR_HZ, JR_LX, JR_LY, JR_LZ, JR_VX, JR_VY, JR_VZ, 
 // bounding box of the predicted positions (origin of the FP32 relative
 // coordinates), the centre of the bounding box of the predicted velocities,
 // the half-diagonal of that velocity box (no velocity of the tile is farther
-// from the centre), the largest mass, and the half-diagonal of the position
-// box (no position of the tile is farther from the origin).
-enum : int { TM_OX = 0, TM_OY, TM_OZ, TM_VX, TM_VY, TM_VZ, TM_W, TM_MMAX, TM_D, kTileMeta };
+// from the centre), the largest mass, the half-diagonal of the position box
+// (no position of the tile is farther from the origin), and the time the
+// particles were predicted to when the frame was formed.
+enum : int { TM_OX = 0, TM_OY, TM_OZ, TM_VX, TM_VY, TM_VZ, TM_W, TM_MMAX, TM_D, TM_T, kTileMeta };
 
 // Per-cluster force plan, written by the plan kernel.
 struct Plan {
@@ -139,8 +140,10 @@ struct DevState {
   double* inter;   // [nc] pairwise interactions evaluated
   int64_t* steps;  // [nc] block steps taken
   double* cm2;     // [2][nch] per chunk: smallest t + dt of the particles the last selection left out
+  int32_t* cm2n;   // [2][nch] per chunk: how many of those particles have that t + dt
   int32_t* acount; // [2][nc] block size of each cluster (selection counters, one half per step parity)
   double* umin;    // [n] per reduce unit: smallest new t + dt of the particles it corrected
+  int32_t* ucnt;   // [n] per reduce unit: how many of those particles have that t + dt
   int32_t* act;    // [n] active list (step pipeline: cluster c's block at act[coff[c]...])
   int64_t* aoff;   // [nc+1] active offsets of the internal all-particle passes
   Plan* plan;      // [nc]
@@ -160,13 +163,19 @@ struct DevState {
 // allows.  Offsets (item_off, slot_base, act_off, red_off) are not set.
 // Integer type T: every intermediate fits in it (32-bit divisions are much
 // shorter than 64-bit ones, and this runs in kernel prologues).
-template <typename T>
-__host__ __device__ inline void plan_layout_t(T na, T nn, T target_items, const int32_t* vmin_all, Plan& P) {
-  const int32_t* vmin = (int64_t)nn < (int64_t)vmin_all[2 * (kNumVariants - 1)] ? vmin_all + (kNumVariants - 1)
-                                                                                   : vmin_all;
+// Layout of a block of na members in a cluster of nn particles: the lowest
+// index whose threshold the block reaches (the last layout has none).
+__host__ __device__ inline int plan_variant(int64_t na, int64_t nn, const int32_t* vmin_all) {
+  const int32_t* vmin = nn < (int64_t)vmin_all[2 * (kNumVariants - 1)] ? vmin_all + (kNumVariants - 1) : vmin_all;
   int var = kNumVariants - 1;
   for (int vv = kNumVariants - 2; vv >= 0; --vv)
-    if ((int64_t)na >= vmin[vv]) var = vv;
+    if (na >= vmin[vv]) var = vv;
+  return var;
+}
+
+template <typename T>
+__host__ __device__ inline void plan_layout_t(T na, T nn, T target_items, const int32_t* vmin_all, Plan& P) {
+  const int var = plan_variant((int64_t)na, (int64_t)nn, vmin_all);
   const T iwg = (T)variant_iwg(var);
   const T chunks = (na + iwg - 1) / iwg;
   T S = 1;

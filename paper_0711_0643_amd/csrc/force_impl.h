@@ -686,6 +686,14 @@ __device__ void run_item(const DevState& s, const int32_t* __restrict__ act, con
   const int64_t j_begin = c_begin + (int64_t)slice * P.slice_len;
   int64_t j_end = j_begin + P.slice_len;
   if (j_end > c_end) j_end = c_end;
+  // the frames must have been formed at the cluster's prediction time (the
+  // selection forms them only for blocks that read them, all of a cluster's
+  // or none): checked on the item's first tile, off the sweep's registers
+  if constexpr (FRAME) {
+    if (tid == 0 && j_begin < j_end &&
+        s.tmeta[(int64_t)(s.cl_ch[c] + (int)((j_begin - c_begin) / kTile)) * kTileMeta + TM_T] != s.tpred[c])
+      __hip_atomic_fetch_or(s.status, (int32_t)ST_STATE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
 
   for (int64_t j0 = j_begin; j0 < j_end; j0 += kTile) {
     // frame of this tile (selection chunk), the same for every thread

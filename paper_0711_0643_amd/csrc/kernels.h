@@ -47,8 +47,10 @@ hipError_t launch_reduce(const DevState& s, const int64_t* aoff, int64_t n_activ
 // sum handed straight to the corrector (pot: keep phi); records the smallest
 // new t + dt per reduce unit for the next selection and clears the
 // selection counters of the other parity.  par, target_items: as for
-// launch_force.
-hipError_t launch_reduce_correct_step(const DevState& s, bool pot, int par, int64_t target_items, hipStream_t st);
+// launch_force; counting: as for launch_select (also records how many
+// particles of a unit have its smallest t + dt).
+hipError_t launch_reduce_correct_step(const DevState& s, bool pot, int par, int64_t target_items, bool counting,
+                                      hipStream_t st);
 
 // Predict every particle of every cluster to s.tpred[c] (FP64 x_p, v_p,
 // every field of the mixed j-records and the tile frames).
@@ -76,7 +78,11 @@ hipError_t launch_correct(const DevState& s, const int32_t* act, const int64_t* 
 // again whenever t, dt or the plan changed outside the step pipeline.
 hipError_t launch_select_init(const DevState& s, int par, hipStream_t st);
 // mode: force mode of the step (the predictor writes only what it reads).
-hipError_t launch_select(const DevState& s, int64_t target_items, int mode, int par, hipStream_t st);
+// counting: derive each cluster's block size before the predictor runs, so
+// that the tile-relative frames are formed only for blocks that take the
+// one-lane-per-i layout (needed when some cluster can reach that layout;
+// must stay the same from launch_select_init to the next one).
+hipError_t launch_select(const DevState& s, int64_t target_items, int mode, int par, bool counting, hipStream_t st);
 
 // Mean relative error b of the FP32 hardware reciprocal square root over
 // log-uniform arguments in [1, 4); sets ctl->rsq_scale3 = 1 - 3b and

@@ -14,6 +14,32 @@ __device__ __forceinline__ void set_status(const DevState& s, int32_t bit) {
   __hip_atomic_fetch_or(s.status, bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// (smallest value, how many have it) of two such pairs.  A NaN never counts.
+__device__ __forceinline__ void min_count(double& v, int32_t& n, double ov, int32_t on) {
+  const double m = fmin(v, ov);
+  n = (v == m ? n : 0) + (ov == m ? on : 0);
+  v = m;
+}
+
+// The workgroup's smallest v and the number of its threads' counts n at
+// that value; every thread gets both.  The waves are combined in a fixed
+// order (the count is exact in any order).
+__device__ __forceinline__ double block_min_count(double v, int32_t& n, double* buf, int32_t* nbuf) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) min_count(v, n, __shfl_xor(v, o), __shfl_xor(n, o));
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) {
+    buf[threadIdx.x >> 6] = v;
+    nbuf[threadIdx.x >> 6] = n;
+  }
+  __syncthreads();
+  double r = buf[0];
+  int32_t rn = nbuf[0];
+  for (int w = 1; w < (int)(blockDim.x >> 6); ++w) min_count(r, rn, buf[w], nbuf[w]);
+  n = rn;
+  return r;
+}
+
 // ---------------------------------------------------------------------------
 // Hermite predictor (Sect. 2.1, predictor equations) for particle i to time
 // tp.  Writes what the force pass of `mode` and the corrector read:
@@ -75,11 +101,13 @@ __device__ __forceinline__ void predict_from(const DevState& s, int64_t i, const
 // Frame of selection chunk ch (= LDS tile) from the predicted positions and
 // velocities of its particles (`have`: this thread holds one), for the
 // mixed modes: bounding-box centres of positions and velocities, the
-// half-diagonals of the velocity and position boxes and the largest mass.  Called by every
-// thread of the workgroup; min / max are exact, so the frame does not
-// depend on the reduction order.
+// half-diagonals of the velocity and position boxes, the largest mass and
+// the prediction time tp (the force pass checks that a frame it reads was
+// formed at its cluster's prediction time).  Called by every thread of the
+// workgroup; min / max are exact, so the frame does not depend on the
+// reduction order.
 __device__ __forceinline__ void tile_frame(const DevState& s, int ch, bool have, const double xp[3], const double vp[3],
-                                           double m) {
+                                           double m, double tp) {
   __shared__ double red[kSelThreads / 64][13];
   const int tid = threadIdx.x;
   double lo[6], hi[6], mm = have ? m : 0.0;
@@ -135,6 +163,7 @@ __device__ __forceinline__ void tile_frame(const DevState& s, int ch, bool have,
     f[TM_W] = 0.5 * sqrt(w2);
     f[TM_MMAX] = mm;
     f[TM_D] = 0.5 * sqrt(d2);
+    f[TM_T] = tp;
   }
 }
 
@@ -147,11 +176,12 @@ __global__ void __launch_bounds__(kSelThreads) predict_all_kernel(DevState s) {
   const bool have = i < s.ch_begin[ch + 1];
   double xp[3] = {0.0, 0.0, 0.0}, vp[3] = {0.0, 0.0, 0.0};
   double m = 0.0;
+  const double tp = s.tpred[s.ch_cluster[ch]];
   if (have) {
-    predict_from(s, i, load_pred(s, i), s.tpred[s.ch_cluster[ch]], kAllRecords, true, xp, vp);
+    predict_from(s, i, load_pred(s, i), tp, kAllRecords, true, xp, vp);
     m = s.m[i];
   }
-  tile_frame(s, ch, have, xp, vp, m);
+  tile_frame(s, ch, have, xp, vp, m, tp);
 }
 
 hipError_t launch_predict_all(const DevState& s, hipStream_t st) {
@@ -430,10 +460,11 @@ __device__ __forceinline__ int cluster_of_unit(const Plan* plan, int nc, int64_t
 
 // The reduce work units [blockIdx.x, units) in steps of gridDim.x.  SINGLE:
 // the only cluster's plan is P1 (step pipeline); otherwise from s.plan.
-template <bool STEP, bool SINGLE>
+template <bool STEP, bool SINGLE, bool COUNT>
 __device__ __forceinline__ void reduce_units(const DevState& s, int64_t units, const Plan& P1, int64_t n_active,
                                              double* acc, double* jerk, double* pot, int64_t stride,
-                                             double* wave_min, double (*wave_sum)[256 / 64], int64_t* offs_sh) {
+                                             double* wave_min, int32_t* wave_cnt, double (*wave_sum)[256 / 64],
+                                             int64_t* offs_sh) {
   const int tid = threadIdx.x;
   const int64_t rows_cap = s.rows_cap;
   // batches of up to kLdsClusters: the unit offsets in LDS for the lookup
@@ -518,22 +549,40 @@ __device__ __forceinline__ void reduce_units(const DevState& s, int64_t units, c
       }
     }
     if constexpr (STEP) {
-      // smallest new t + dt of the unit, for the next block selection
+      // smallest new t + dt of the unit (and, when the selection counts
+      // block sizes, how many of its particles have it), for the next block
+      // selection
+      int32_t cnt = t_next < INFINITY ? 1 : 0;
+      if constexpr (COUNT) {
 #pragma unroll
-      for (int o = 32; o >= 1; o >>= 1) t_next = fmin(t_next, __shfl_xor(t_next, o));
-      if ((tid & 63) == 0) wave_min[tid >> 6] = t_next;
+        for (int o = 32; o >= 1; o >>= 1) min_count(t_next, cnt, __shfl_xor(t_next, o), __shfl_xor(cnt, o));
+      } else {
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) t_next = fmin(t_next, __shfl_xor(t_next, o));
+      }
+      if ((tid & 63) == 0) {
+        wave_min[tid >> 6] = t_next;
+        wave_cnt[tid >> 6] = cnt;
+      }
       __syncthreads();
-      if (tid == 0) s.umin[u] = fmin(fmin(wave_min[0], wave_min[1]), fmin(wave_min[2], wave_min[3]));
+      if (tid == 0) {
+        double m = wave_min[0];
+        int32_t k = wave_cnt[0];
+        for (int w = 1; w < 4; ++w) min_count(m, k, wave_min[w], wave_cnt[w]);
+        s.umin[u] = m;
+        if (COUNT) s.ucnt[u] = k;
+      }
     }
     __syncthreads();  // wave_min and wave_sum are reused by the next unit
   }
 }
 
-template <bool STEP>
+template <bool STEP, bool COUNT = false>
 __global__ void __launch_bounds__(256) reduce_kernel(DevState s, const int64_t* __restrict__ aoff,
                                                      int64_t n_bound, int n_from_aoff, double* acc, double* jerk,
                                                      double* pot, int64_t stride, int par, int64_t target_items) {
   __shared__ double wave_min[256 / 64];
+  __shared__ int32_t wave_cnt[256 / 64];
   __shared__ double wave_sum[7][256 / 64];
   __shared__ int64_t offs_sh[kLdsClusters];
   const int tid = threadIdx.x;
@@ -560,11 +609,13 @@ __global__ void __launch_bounds__(256) reduce_kernel(DevState s, const int64_t* 
   }
   if constexpr (STEP) {
     if (single) {
-      reduce_units<true, true>(s, units, P1, n_active, acc, jerk, pot, stride, wave_min, wave_sum, offs_sh);
+      reduce_units<true, true, COUNT>(s, units, P1, n_active, acc, jerk, pot, stride, wave_min, wave_cnt, wave_sum,
+                                      offs_sh);
       return;
     }
   }
-  reduce_units<STEP, false>(s, units, P1, n_active, acc, jerk, pot, stride, wave_min, wave_sum, offs_sh);
+  reduce_units<STEP, false, COUNT>(s, units, P1, n_active, acc, jerk, pot, stride, wave_min, wave_cnt, wave_sum,
+                                   offs_sh);
 }
 
 
@@ -592,12 +643,17 @@ hipError_t launch_reduce(const DevState& s, const int64_t* aoff, int64_t n_activ
   return hipGetLastError();
 }
 
-hipError_t launch_reduce_correct_step(const DevState& s, bool pot, int par, int64_t target_items, hipStream_t st) {
+hipError_t launch_reduce_correct_step(const DevState& s, bool pot, int par, int64_t target_items, bool counting,
+                                      hipStream_t st) {
   // pot only flags whether the potential row exists; the step writes s.pot.
   // The active list holds each cluster's block in its own segment, so every
   // entry index is below n.
-  hipLaunchKernelGGL(reduce_kernel<true>, dim3(kReduceGrid), dim3(256), 0, st, s, s.aoff, s.n, 0,
-                     (double*)nullptr, (double*)nullptr, pot ? s.pot : nullptr, (int64_t)0, par, target_items);
+  if (counting)
+    hipLaunchKernelGGL((reduce_kernel<true, true>), dim3(kReduceGrid), dim3(256), 0, st, s, s.aoff, s.n, 0,
+                       (double*)nullptr, (double*)nullptr, pot ? s.pot : nullptr, (int64_t)0, par, target_items);
+  else
+    hipLaunchKernelGGL((reduce_kernel<true, false>), dim3(kReduceGrid), dim3(256), 0, st, s, s.aoff, s.n, 0,
+                       (double*)nullptr, (double*)nullptr, pot ? s.pot : nullptr, (int64_t)0, par, target_items);
   return hipGetLastError();
 }
 
@@ -810,17 +866,21 @@ __device__ __forceinline__ double block_min(double v, double* buf) {
 }
 
 // Start of a run of steps (after the state or the plan changed outside the
-// step pipeline): cm2 = the chunk minima of t + dt, no corrected particles.
+// step pipeline): cm2 = the chunk minima of t + dt, cm2n = how many
+// particles of the chunk have that t + dt, no corrected particles.
 __global__ void __launch_bounds__(kSelThreads) select_init_kernel(DevState s, int par) {
   __shared__ double buf[kSelThreads / 64];
+  __shared__ int32_t nbuf[kSelThreads / 64];
   const int ch = blockIdx.x;
   const int c = s.ch_cluster[ch];
   const int64_t b = s.ch_begin[ch], e = s.ch_begin[ch + 1];
   double mn = INFINITY;
-  for (int64_t i = b + threadIdx.x; i < e; i += kSelThreads) mn = fmin(mn, s.t[i] + s.dt[i]);
-  mn = block_min(mn, buf);
+  int32_t cnt = 0;
+  for (int64_t i = b + threadIdx.x; i < e; i += kSelThreads) min_count(mn, cnt, s.t[i] + s.dt[i], 1);
+  mn = block_min_count(mn, cnt, buf, nbuf);
   if (threadIdx.x == 0) {
     s.cm2[par * s.nch + ch] = mn;
+    s.cm2n[par * s.nch + ch] = cnt;
     if (ch == s.cl_ch[c]) {
       s.plan[c].n_act = 0;
       s.acount[c] = 0;
@@ -829,18 +889,19 @@ __global__ void __launch_bounds__(kSelThreads) select_init_kernel(DevState s, in
   }
 }
 
-// Whether a block of cluster c can reach the one-lane-per-i layout under
-// the current thresholds (the cluster is at least as large as that layout's
-// smallest block).
-__device__ __forceinline__ bool tr_layout_reachable(const DevState& s, int c) {
-  const int64_t nn = s.coff[c + 1] - s.coff[c];
-  const int64_t thr = nn < s.ctl->small_n ? s.ctl->vmin_small[1] : s.ctl->vmin[1];
-  return nn >= thr;
+// Whether a block of na members of cluster c takes a one-lane-per-i layout
+// (the same decision as the plan's).
+__device__ __forceinline__ bool takes_one_lane_layout(const DevState& s, int c, int64_t na) {
+  int32_t vmin_all[2 * (kNumVariants - 1) + 1];
+  load_thresholds(s.ctl, vmin_all);
+  return plan_variant(na, s.coff[c + 1] - s.coff[c], vmin_all) <= 1;
 }
 
+template <bool COUNT>
 __global__ void __launch_bounds__(kSelThreads) select_kernel(DevState s, int mode, int par, int64_t target_items) {
   static_assert(kSelChunk == kSelThreads, "one particle per thread");
   __shared__ double buf[kSelThreads / 64];
+  __shared__ int32_t nbuf[kSelThreads / 64];
   __shared__ int64_t sbuf[kSelThreads / 64];
   __shared__ int64_t base_sh;
   const int ch = blockIdx.x;
@@ -848,6 +909,8 @@ __global__ void __launch_bounds__(kSelThreads) select_kernel(DevState s, int mod
   const int tid = threadIdx.x;
   const double* cur = s.cm2 + (int64_t)par * s.nch;
   double* nxt = s.cm2 + (int64_t)(par ^ 1) * s.nch;
+  const int32_t* curn = s.cm2n + (int64_t)par * s.nch;
+  int32_t* nxtn = s.cm2n + (int64_t)(par ^ 1) * s.nch;
 
   // this thread's particle: its t + dt and (for a cluster that has not
   // reached the end time) the predictor's inputs do not depend on the block
@@ -862,7 +925,10 @@ __global__ void __launch_bounds__(kSelThreads) select_kernel(DevState s, int mod
     // the cluster has reached the end time (so it takes no step: every
     // particle is at t_end) and took none last step either: the chunk's
     // minimum of t + dt is unchanged, nothing else to do
-    if (tid == 0) nxt[ch] = cur[ch];
+    if (tid == 0) {
+      nxt[ch] = cur[ch];
+      nxtn[ch] = curn[ch];
+    }
     return;
   }
   double tt = INFINITY;
@@ -873,15 +939,29 @@ __global__ void __launch_bounds__(kSelThreads) select_kernel(DevState s, int mod
     tt = pin.t + s.dt[i];
   }
 
-  // block time of cluster c
+  // block time of cluster c and, where it decides whether the tile frames
+  // are formed (COUNT: tile-relative format with some cluster that can
+  // reach the one-lane-per-i layout; the same for every step between two
+  // initialisations), the size of its block: a particle at the block time
+  // is either one the last selection left out (counted per chunk at the
+  // chunk's minimum) or one the last step corrected (counted per reduce
+  // unit at the unit's minimum), so the sizes of the minima equal to the
+  // block time add up to the block size
   double mn = INFINITY;
-  for (int f = s.cl_ch[c] + tid; f < s.cl_ch[c + 1]; f += kSelThreads) mn = fmin(mn, cur[f]);
-  if (P.n_act > 0) {
-    const int64_t epw = 256 / P.red_tp;
-    const int64_t units = (P.n_act + epw - 1) / epw;
+  int32_t nblock = 0;
+  const int64_t epw = 256 / P.red_tp;
+  const int64_t units = P.n_act > 0 ? (P.n_act + epw - 1) / epw : 0;
+  double tsys;
+  if constexpr (COUNT) {
+    for (int f = s.cl_ch[c] + tid; f < s.cl_ch[c + 1]; f += kSelThreads) min_count(mn, nblock, cur[f], curn[f]);
+    for (int64_t u = tid; u < units; u += kSelThreads)
+      min_count(mn, nblock, s.umin[P.red_off + u], s.ucnt[P.red_off + u]);
+    tsys = block_min_count(mn, nblock, buf, nbuf);
+  } else {
+    for (int f = s.cl_ch[c] + tid; f < s.cl_ch[c + 1]; f += kSelThreads) mn = fmin(mn, cur[f]);
     for (int64_t u = tid; u < units; u += kSelThreads) mn = fmin(mn, s.umin[P.red_off + u]);
+    tsys = block_min(mn, buf);
   }
-  const double tsys = block_min(mn, buf);
   // an error recorded on the device (step underflow, non-finite value, bad
   // index) freezes the state: no cluster advances, so this step and every
   // later one select nothing and change nothing; the status word was written
@@ -893,17 +973,23 @@ __global__ void __launch_bounds__(kSelThreads) select_kernel(DevState s, int mod
   if (have && advancing) predict_from(s, i, ahead ? pin : load_pred(s, i), tsys, mode, member, xo, vo);
   // the mixed force pass reads the tile frame of every chunk of an
   // advancing cluster (the condition is the same for the whole workgroup);
-  // the tile-relative mode only in clusters large enough for its
-  // one-lane-per-i layout (its split layouts run the FP64 arithmetic)
-  if (advancing && mode != kF64 && (mode != kTR || tr_layout_reachable(s, c)))
-    tile_frame(s, ch, have, xo, vo, have ? s.m[i] : 0.0);
+  // the tile-relative mode only when this block takes a one-lane-per-i
+  // layout (its split layouts run the FP64 arithmetic)
+  if (advancing && mode != kF64 && (mode != kTR || (COUNT && takes_one_lane_layout(s, c, nblock))))
+    tile_frame(s, ch, have, xo, vo, have ? s.m[i] : 0.0, tsys);
 
-  // members, and the smallest t + dt of the others
-  const double rest = block_min(member ? INFINITY : tt, buf);
+  // members, and the smallest t + dt of the others (with their number)
+  int32_t nrest = have && !member ? 1 : 0;
+  double rest;
+  if constexpr (COUNT)
+    rest = block_min_count(member ? INFINITY : tt, nrest, buf, nbuf);
+  else
+    rest = block_min(member ? INFINITY : tt, buf);
   int64_t total;
   const int64_t before = wg_exclusive_scan(member ? 1 : 0, sbuf, &total);
   if (tid == 0) {
     nxt[ch] = rest;
+    if (COUNT) nxtn[ch] = nrest;
     base_sh = total > 0 ? atomicAdd(&s.acount[(int64_t)par * s.nc + c], (int32_t)total) : 0;
     if (advancing && ch == s.cl_ch[c]) s.tpred[c] = tsys;
   }
@@ -924,8 +1010,11 @@ hipError_t launch_select_init(const DevState& s, int par, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_select(const DevState& s, int64_t target_items, int mode, int par, hipStream_t st) {
-  hipLaunchKernelGGL(select_kernel, dim3(s.nch), dim3(kSelThreads), 0, st, s, mode, par, target_items);
+hipError_t launch_select(const DevState& s, int64_t target_items, int mode, int par, bool counting, hipStream_t st) {
+  if (counting)
+    hipLaunchKernelGGL(select_kernel<true>, dim3(s.nch), dim3(kSelThreads), 0, st, s, mode, par, target_items);
+  else
+    hipLaunchKernelGGL(select_kernel<false>, dim3(s.nch), dim3(kSelThreads), 0, st, s, mode, par, target_items);
   if (s.nc == 1) return hipGetLastError();  // the force and reduce kernels plan for themselves
   int32_t* counts = s.acount + (int64_t)par * s.nc;
   if (s.nc <= 64)

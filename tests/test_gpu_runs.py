@@ -77,6 +77,28 @@ def test_mixed_run_energy_drift_matches_oracle(case):
     sim.close()
 
 
+def test_mixed_run_switching_layouts_matches_oracle():
+    """C1 with the one-lane-per-i layout from blocks of 64 on: most steps
+    switch between the j-split layouts (FP64 arithmetic, no tile frames) and
+    the tile-relative one, whose frames the selection forms only when the
+    block size it derives from the chunk and reduce-unit minima reaches that
+    threshold.  A frame read at another time than it was formed for raises
+    the state status; the run must end with none and follow the oracle run."""
+    import paper_0711_0643_amd as nb
+
+    g = _golden("C1")
+    m, x, v = icgen.plummer(g["n"], g["seed"])
+    banner(f"mixed run C1 N={g['n']}, one lane per i from 64")
+    sim = nb.Sim(m, x, v, g["eps"], precision=nb.MIXED)
+    sim.set_tuning(min_block=[1 << 30, 64, 48, 12], small_cluster_n=0)
+    trace = _run_traced(sim, g["t_end"])
+    ref = np.array([e for _, e in g["energy_trace"]])
+    drift = (trace[-1] - trace[0]) / abs(trace[0])
+    ref_drift = (ref[-1] - ref[0]) / abs(ref[0])
+    assert abs(drift - ref_drift) < 1e-8
+    sim.close()
+
+
 def _batch_traces(sim, t_end):
     traces = [sim.energy()]
     t = 0.0
