@@ -266,6 +266,42 @@ def test_batched_clusters_match_single_runs():
     both.close()
 
 
+def test_batched_mixed_clusters_match_single_runs():
+    """Mixed precision with the one-lane-per-i layout from blocks of 256 on:
+    in the batch every selection counts block sizes and forms the tile frames
+    of the blocks that take that layout, while the 200-particle cluster run
+    alone never reaches it (split-only build, no counting).  Every cluster
+    stays bit-identical to the same cluster integrated alone."""
+    sizes = (200, 700, 1200)
+    parts = [icgen.plummer(n, 70 + n) for n in sizes]
+    m = np.concatenate([p[0] for p in parts])
+    x = np.concatenate([p[1] for p in parts], axis=1)
+    v = np.concatenate([p[2] for p in parts], axis=1)
+    coff = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    eps = np.array([1.0 / n for n in sizes])
+    tuning = dict(small_cluster_n=0, min_block=[1 << 30, 256, 48, 12])
+    banner("batched vs single, mixed, one lane per i from 256")
+    both = _sim(m, x, v, eps, precision=1, coff=coff)
+    both.set_tuning(**tuning)
+    both.run(0.25, chunk=128)
+    assert both.status() == 0
+    sb = both.host_state()
+    _, nb_steps, _ = both.progress()
+    for c in range(len(sizes)):
+        b, e = int(coff[c]), int(coff[c + 1])
+        one = _sim(m[b:e], x[:, b:e], v[:, b:e], eps[c], precision=1)
+        one.set_tuning(**tuning)
+        one.run(0.25, chunk=128)
+        assert one.status() == 0
+        so = one.host_state()
+        for key in ("x", "v", "a", "k"):
+            assert np.array_equal(sb[key][:, b:e], so[key]), (c, key)
+        assert np.array_equal(sb["dt"][b:e], so["dt"])
+        assert one.progress()[1][0] == nb_steps[c]
+        one.close()
+    both.close()
+
+
 def test_finished_batch_idles_then_continues():
     """Clusters of a batch that have reached the end time take no step: more
     step calls leave every bit of the state and the step counts alone, and a
