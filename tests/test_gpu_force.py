@@ -328,6 +328,33 @@ def test_mixed_near_pairs_in_fp64_fix_close_neighbours():
     sim.close()
 
 
+def test_mixed_mid_pairs_fix_pairs_close_against_their_tile():
+    """A pair much closer than its tile is large loses part of its distance
+    in tile-relative FP32 coordinates (error about u L / R) although its term
+    is below the near threshold.  On the N = 65536 Plummer sphere, with the
+    mid replacement off (mid_tau huge) jerks with kappa_k <= 10 miss 1e-6;
+    with it on (default), and with the close pairs of nearly every window
+    replaced (mid_tau = 0.01), acceleration and those jerks pass."""
+    n = 65536
+    m, x, v = icgen.plummer(n, 3)
+    eps = 1.0 / n
+    banner("mid pairs on/off")
+    sim = _sim(m, x, v, eps, 1)
+    act = np.arange(n, dtype=np.int32)
+    ref = oracle.force(m, x, v, eps)
+    kappa = oracle.force_abs(m, x, v, eps)[1] / np.linalg.norm(ref[1], axis=0)
+    errs = {}
+    for tau in (4.0, 0.01, 1e30):
+        sim.set_tuning(mid_tau=tau)
+        a, k, _ = _gpu_force(sim, act)
+        assert sim.status() == 0
+        errs[tau] = (rel_err(a, ref[0]).max(), rel_err(k, ref[1])[kappa <= 10].max())
+    for tau in (4.0, 0.01):
+        assert errs[tau][0] <= 1e-6 and errs[tau][1] <= 1e-6, (tau, errs[tau])
+    assert errs[1e30][1] > 1e-6, errs[1e30]
+    sim.close()
+
+
 @pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
 def test_king_salpeter_n262144_full_block_sampled(precision):
     """King W0 = 6 with Salpeter masses, N = 262144, eps = 1/N, every
