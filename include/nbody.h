@@ -66,7 +66,11 @@ typedef enum {
     NBODY_E_INVAL = -1,     /* bad argument (host-side validation)               */
     NBODY_E_NOMEM = -2,     /* workspace too small / host allocation failed      */
     NBODY_E_HIP = -3,       /* a HIP runtime call failed                         */
-    NBODY_E_STATE = -4,     /* call out of order (e.g. correct before predict)   */
+    NBODY_E_STATE = -4,     /* call out of order (e.g. correct before predict);
+                               device: an internal inconsistency (a work item
+                               of a layout its kernel build does not hold, a
+                               tile frame formed for another time, a
+                               corrector step that does not advance)          */
     NBODY_E_DTMIN = -5,     /* device: a new step fell below dt_min              */
     NBODY_E_NONFINITE = -6, /* device: non-finite position, velocity or force    */
     NBODY_E_INDEX = -7      /* device: active index outside its cluster or

@@ -16,7 +16,8 @@ enum : int32_t {
   ST_INDEX = 1,      // active index outside its cluster / bad active offsets
   ST_NONFINITE = 2,  // non-finite x, v, a or k, or NaN step criterion
   ST_DTMIN = 4,      // new step below dt_min
-  ST_STATE = 8,      // corrector asked to step by a non-positive time, or a force work item of a layout the launched kernel lacks
+  ST_STATE = 8,      // corrector asked to step by a non-positive time, a force work item of a layout the launched
+                     // kernel lacks, or a tile frame formed for another time than its cluster's prediction
 };
 
 // Batches of up to this many clusters look up the cluster of a work item in
