@@ -79,7 +79,7 @@ def calibrate_copy():
 
 
 # the sources the force kernel is compiled from
-FORCE_SOURCES = ("force.hip", "force_impl.h", "force_tuned.hip", "common.h", "kernels.h")
+FORCE_SOURCES = ("force.hip", "force_impl.h", "force_tuned.hip", "force_tuned_t128.hip", "common.h", "kernels.h")
 
 
 def recorded_traffic():
@@ -588,8 +588,8 @@ def main():
             "unit": "TFLOP/s",
             "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
             "traffic": recorded_traffic(),
-            "kernel": "nb::force_kernel<3, false, true, false, true, 32, 4> (mixed tile-relative, no potential, "
-                      "near pairs, lean; FP32 window 32, 4 waves per SIMD)",
+            "kernel": "nb::force_kernel<3, false, true, false, true, 32, 4, 256> (mixed tile-relative, no potential, "
+                      "near pairs, lean; FP32 window 32, 4 waves per SIMD, 256-record j-tiles)",
             "flops_per_interaction": FLOPS_ACC_JERK,
             "flop_count_rule": "algorithmic acc + jerk without the potential (FMA = 2, rsqrt = 1); 42 with it",
             "interactions_per_launch": inter_step,

@@ -304,13 +304,15 @@ NBODY_API nbody_status nbody_get_layout(const nbody_ctx *ctx, nbody_layout *out)
  *                 is summed again with FP64 position differences (L: the
  *                 i's distance from the tile centre plus the tile's size;
  *                 default 4).
- *   window, waves: build of the tile-relative kernel with the near test on
- *                 the lean path (every cluster softened) and no potential:
- *                 FP32 window of 16, 32 or 64 pairs and an occupancy of 2
- *                 to 5 waves per SIMD (default 32 and 4, the build that
- *                 needs no scratch memory; results change
- *                 at rounding level with the window).  Other passes use
- *                 their own fixed build.
+ *   window, waves, tile: build of the tile-relative kernel with the near
+ *                 test on the lean path (every cluster softened) and no
+ *                 potential: FP32 window of 16, 32 or 64 pairs, an
+ *                 occupancy of 2 to 5 waves per SIMD and j-tiles of 128 or
+ *                 256 records in LDS (128 only with windows of 16 or 32;
+ *                 NBODY_E_INVAL otherwise; default 32, 4 and 256, the build that
+ *                 needs no scratch memory; results change at rounding level
+ *                 with the window and the tile).  Other passes use their
+ *                 own fixed build.
  *   reserved: must be 0.
  * In the tile-relative format the mixed arithmetic runs in the
  * one-lane-per-i layout (blocks from min_block[1] on); the layouts that
@@ -329,7 +331,8 @@ typedef struct {
     double mid_tau;
     int32_t window;
     int32_t waves;
-    int32_t reserved[2];
+    int32_t tile;
+    int32_t reserved;
 } nbody_tuning;
 NBODY_API nbody_status nbody_get_tuning(const nbody_ctx *ctx, nbody_tuning *out);
 NBODY_API nbody_status nbody_set_tuning(nbody_ctx *ctx, const nbody_tuning *t);

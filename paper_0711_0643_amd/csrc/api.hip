@@ -200,6 +200,7 @@ struct nbody_ctx {
   int mixed_mode = kTR;   // position format of the mixed kernel
   int kwindow = 32;       // FP32 window of the lean tile-relative kernel (16, 32, 64)
   int kwaves = 4;         // its occupancy, waves per SIMD (2 to 5)
+  int ktile = kTile;      // its j-records per LDS tile (128 or 256)
   int rsq_correct = 1;    // remove the mean bias of v_rsq_f32 in the mixed kernel
   hipGraph_t graph[2] = {nullptr, nullptr};
   hipGraphExec_t gexec[2] = {nullptr, nullptr};  // one block step, of parity 0 and 1
@@ -329,7 +330,7 @@ hipError_t capture_steps(nbody_ctx* c, int steps, int par0, hipGraph_t* g) {
     e = launch_select(s, c->target_items, mode, par, counting, c->cap_stream);
     if (e == hipSuccess)
       e = launch_force(s, mode, c->p.compute_pot != 0, c->ctl.near_tau > 0.0, split_only(c, s.n), c->lean_ok, s.act,
-                       c->grid, par, c->target_items, c->cap_stream, c->kwindow, c->kwaves);
+                       c->grid, par, c->target_items, c->cap_stream, c->kwindow, c->kwaves, c->ktile);
     if (e == hipSuccess)
       e = launch_reduce_correct_step(s, c->p.compute_pot != 0, par, c->target_items, counting, c->cap_stream);
   }
@@ -630,7 +631,7 @@ nbody_status force_pass(nbody_ctx* c, const DevState& s, const int32_t* active_i
   }
   HIP_OK(launch_force(s, force_mode(c), pot != nullptr, c->ctl.near_tau > 0.0, split_only(c, n_active), c->lean_ok,
                       s.ulist,
-                      c->grid, -1, c->target_items, c->stream, c->kwindow, c->kwaves));
+                      c->grid, -1, c->target_items, c->stream, c->kwindow, c->kwaves, c->ktile));
   if (profile) {
     HIP_OK(hipEventRecord(ev.second, c->stream));
     c->prof_pending.push_back(ev);
@@ -893,7 +894,8 @@ nbody_status nbody_get_tuning(const nbody_ctx* c, nbody_tuning* t) {
   t->mid_tau = c->ctl.mid_tau;
   t->window = c->kwindow;
   t->waves = c->kwaves;
-  t->reserved[0] = t->reserved[1] = 0;
+  t->tile = c->ktile;
+  t->reserved = 0;
   return NBODY_OK;
 }
 
@@ -911,8 +913,9 @@ nbody_status nbody_set_tuning(nbody_ctx* c, const nbody_tuning* t) {
     if (i > 0 && t->min_block[i - 1] < t->min_block[i]) return NBODY_E_INVAL;
     if (i > 0 && t->small_min_block[i - 1] < t->small_min_block[i]) return NBODY_E_INVAL;
   }
-  if (t->small_cluster_n < 0 || t->reserved[0] != 0 || t->reserved[1] != 0) return NBODY_E_INVAL;
+  if (t->small_cluster_n < 0 || t->reserved != 0) return NBODY_E_INVAL;
   if ((t->window != 16 && t->window != 32 && t->window != 64) || t->waves < 2 || t->waves > 5) return NBODY_E_INVAL;
+  if ((t->tile != 128 && t->tile != kTile) || (t->tile == 128 && t->window == 64)) return NBODY_E_INVAL;
   c->target_items = t->target_items;
   c->grid = t->grid;
   c->mixed_mode = t->mixed_format == 2 ? kTR : t->mixed_format == 1 ? kMX64 : kDS;
@@ -923,6 +926,7 @@ nbody_status nbody_set_tuning(nbody_ctx* c, const nbody_tuning* t) {
   c->ctl.mid_tau = t->mid_tau;
   c->kwindow = t->window;
   c->kwaves = t->waves;
+  c->ktile = t->tile;
   for (int i = 0; i < kNumVariants - 1; ++i) c->ctl.vmin[i] = t->min_block[i];
   for (int i = 0; i < kNumVariants - 1; ++i) c->ctl.vmin_small[i] = t->small_min_block[i];
   c->ctl.small_n = t->small_cluster_n;

@@ -37,7 +37,7 @@ static hipError_t launch_family(const ForceLaunch& L, int mode, bool pot, bool n
       } else if (near && L.lean) {
         // the default builds that need no scratch memory: 4 waves per SIMD
         // without the potential, 3 with it
-        if (!pot && (L.window != 32 || L.waves != 4)) return launch_force_tuned(L);
+        if (!pot && (L.window != 32 || L.waves != 4 || L.tile != kTile)) return launch_force_tuned(L);
         if (pot)
           hipLaunchKernelGGL((force_kernel<kTR, true, true, false, true, 32, 3>), dim3(L.grid), dim3(kForceThreads), 0,
                              L.st, L.s, L.act, L.par, L.target_items);
@@ -56,8 +56,8 @@ static hipError_t launch_family(const ForceLaunch& L, int mode, bool pot, bool n
 }
 
 hipError_t launch_force(const DevState& s, int mode, bool pot, bool near, bool split, bool lean, const int32_t* act,
-                        int grid, int par, int64_t target_items, hipStream_t st, int window, int waves) {
-  const ForceLaunch L{s, act, grid, par, lean, target_items, st, window, waves};
+                        int grid, int par, int64_t target_items, hipStream_t st, int window, int waves, int tile) {
+  const ForceLaunch L{s, act, grid, par, lean, target_items, st, window, waves, tile};
   return split ? launch_family<true>(L, mode, pot, near) : launch_family<false>(L, mode, pot, near);
 }
 

@@ -495,7 +495,7 @@ __device__ __forceinline__ void mid_windows(const DevState& s, const RecTR* tile
 // term above near_tau_k |k_i|; with per-pair weights gsel = g * 2^40 and
 // ksel = (near_tau_k |k_i| / (2 v)) * 2^40, the m_j / R^3 above which a
 // jerk term may exceed it (v bounds |v_j - v_i| over the tile).
-template <int MODE, int PER, int IPT, bool MASK, bool POT, bool NEAR, bool LEANW = false, int FW = 32>
+template <int MODE, int PER, int IPT, bool MASK, bool POT, bool NEAR, bool LEANW = false, int FW = 32, int TJ = kTile>
 __device__ __forceinline__ void sweep_tile(const DevState& s, const typename ModeT<MODE>::Rec* tile,
                                            const RecP64* tile64, const float* wmax, int jl0, const int* own,
                                            int jend, const int64_t* i_glob, const typename ModeT<MODE>::I* I,
@@ -514,7 +514,7 @@ __device__ __forceinline__ void sweep_tile(const DevState& s, const typename Mod
       }
     }
   } else {
-    constexpr bool WIN = NEAR && PER == kTile;  // window test
+    constexpr bool WIN = NEAR && PER == TJ;  // window test
     constexpr bool WGT = NEAR && !WIN;          // per-pair weights
     constexpr int F = PER < FW ? PER : FW;      // FP32 window, then flush to FP64
     constexpr int NW = PER / F;                 // windows per tile
@@ -542,7 +542,7 @@ __device__ __forceinline__ void sweep_tile(const DevState& s, const typename Mod
 #pragma unroll
         for (int p = 0; p < IPT; ++p) {
           Diff32 D;
-          if constexpr (MODE == kTR && PER != kTile)
+          if constexpr (MODE == kTR && PER != TJ)
             D = diff32_tr64(J, tile64[jl], I[p], xi64[p], eps2f);
           else
             D = diff32<MODE>(I[p], J, eps2f);
@@ -611,19 +611,19 @@ __device__ __forceinline__ int find_cluster(const Plan* plan, int nc, int64_t it
 // adds exactly nothing to a and k, and its window is always redone in FP64
 // (which skips it); padding records sit at 1e15, where every term is zero.
 // Without the masked copy of the sweep the kernel needs far fewer registers.
-template <int MODE, int JL, int IPT, bool POT, bool NEAR, bool LEAN = false, int FW = 32>
+template <int MODE, int JL, int IPT, bool POT, bool NEAR, bool LEAN = false, int FW = 32, int TJ = kTile>
 __device__ void run_item(const DevState& s, const int32_t* __restrict__ act, const Plan& P, int c,
                          int64_t local_item, unsigned char* lds, float* wmax) {
   static_assert(JL == 1 || IPT == 1, "several i per lane only with one lane per i");
   constexpr int SLOTS = kForceThreads / JL;  // i-slots per pass
   constexpr int IWG = SLOTS * IPT;
-  constexpr int PER = kTile / JL;
+  constexpr int PER = TJ / JL;
   constexpr bool FRAME = MODE == kTR || (NEAR && MODE != kF64);  // reads the tile frames
   constexpr bool LEANW = LEAN && JL == 1 && NEAR && MODE == kTR;
   constexpr float kPad = LEANW ? 1e15f : 0.f;  // position of padding records
   using Rec = typename ModeT<MODE>::Rec;
   using IT = typename ModeT<MODE>::I;
-  constexpr bool WIN = NEAR && PER == kTile;  // window test (else per-pair weights)
+  constexpr bool WIN = NEAR && PER == TJ;  // window test (else per-pair weights)
   Rec* tile = reinterpret_cast<Rec*>(lds);
   RecP64* tile64 = reinterpret_cast<RecP64*>(lds + kTile * sizeof(RecTR));  // kTR only
 
@@ -695,7 +695,7 @@ __device__ void run_item(const DevState& s, const int32_t* __restrict__ act, con
       __hip_atomic_fetch_or(s.status, (int32_t)ST_STATE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 
-  for (int64_t j0 = j_begin; j0 < j_end; j0 += kTile) {
+  for (int64_t j0 = j_begin; j0 < j_end; j0 += TJ) {
     // frame of this tile (selection chunk), the same for every thread
     double fo[3] = {0.0, 0.0, 0.0}, fv[3] = {0.0, 0.0, 0.0};
     float f_w = 0.f, f_mmax = 0.f, f_d = 0.f;
@@ -711,15 +711,18 @@ __device__ void run_item(const DevState& s, const int32_t* __restrict__ act, con
       f_d = (float)f[TM_D];
     }
     __syncthreads();  // previous tile fully consumed
-    static_assert(kTile == kForceThreads, "one record per thread");
+    // at most one record per thread; a tile lies inside one selection chunk
+    // (slices start at multiples of kTile), whose frame it uses
+    static_assert(TJ <= kForceThreads && kTile % TJ == 0, "tile of at most one record per thread");
     {
       const int64_t j = j0 + tid;
+      const bool loads = tid < TJ && j < j_end;
       float mrec;
       if constexpr (MODE == kTR) {
         RecTR r = zero_rec<kTR>();
         r.x = r.y = r.z = kPad;
         RecP64 q{(double)kPad, (double)kPad, (double)kPad, 0.0, 0.0, 0.0};
-        if (j < j_end) {
+        if (loads) {
           q = load_p64(s, j);
           r.x = (float)(q.x - fo[0]);
           r.y = (float)(q.y - fo[1]);
@@ -733,7 +736,7 @@ __device__ void run_item(const DevState& s, const int32_t* __restrict__ act, con
         tile64[tid] = q;
         mrec = r.m;
       } else {
-        const Rec rec = (j < j_end) ? load_rec<MODE>(s, j) : zero_rec<MODE>();
+        const Rec rec = loads ? load_rec<MODE>(s, j) : zero_rec<MODE>();
         tile[tid] = rec;
         mrec = (float)rec.m;
       }
@@ -809,19 +812,19 @@ __device__ void run_item(const DevState& s, const int32_t* __restrict__ act, con
 #pragma unroll
     for (int p = 0; p < IPT; ++p) {
       const int64_t d = i_glob[p] - j0;
-      own[p] = (valid[p] && d >= 0 && d < kTile) ? (int)d : -1;
+      own[p] = (valid[p] && d >= 0 && d < TJ) ? (int)d : -1;
       mine |= own[p] >= 0;
     }
-    const int jend = (int)(j_end - j0 < kTile ? j_end - j0 : kTile);
-    const bool need_mask = !LEANW && (jend < kTile || __any(mine));
+    const int jend = (int)(j_end - j0 < TJ ? j_end - j0 : TJ);
+    const bool need_mask = !LEANW && (jend < TJ || __any(mine));
     if constexpr (LEANW)
-      sweep_tile<MODE, PER, IPT, false, POT, NEAR, true, FW>(s, tile, tile64, wmax, jl * PER, own, jend, i_glob, I,
+      sweep_tile<MODE, PER, IPT, false, POT, NEAR, true, FW, TJ>(s, tile, tile64, wmax, jl * PER, own, jend, i_glob, I,
                                                              xi64, gsel, ksel, mthr, eps2d, eps2f, ca, cp, A);
     else if (need_mask)
-      sweep_tile<MODE, PER, IPT, true, POT, NEAR, false, FW>(s, tile, tile64, wmax, jl * PER, own, jend, i_glob, I,
+      sweep_tile<MODE, PER, IPT, true, POT, NEAR, false, FW, TJ>(s, tile, tile64, wmax, jl * PER, own, jend, i_glob, I,
                                                              xi64, gsel, ksel, mthr, eps2d, eps2f, ca, cp, A);
     else
-      sweep_tile<MODE, PER, IPT, false, POT, NEAR, false, FW>(s, tile, tile64, wmax, jl * PER, own, jend, i_glob, I,
+      sweep_tile<MODE, PER, IPT, false, POT, NEAR, false, FW, TJ>(s, tile, tile64, wmax, jl * PER, own, jend, i_glob, I,
                                                               xi64, gsel, ksel, mthr, eps2d, eps2f, ca, cp, A);
   }
 
@@ -877,13 +880,17 @@ __device__ void run_item(const DevState& s, const int32_t* __restrict__ act, con
 // that step parity's selection count (plan_single); otherwise it is read
 // from s.plan.
 // FW: the FP32 window (16, 32 or 64 pairs); WPE: the occupancy the
-// compiler is held to (waves per SIMD).  Builds other than FW = 32 with the
-// default occupancy are made only of the lean tile-relative kernel without
-// the potential (the autotuner's candidates).
-template <int MODE, bool POT, bool NEAR, bool SPLIT, bool LEAN, int FW = 32, int WPE = (SPLIT ? 4 : 3)>
+// compiler is held to (waves per SIMD); TJ: j-records per LDS tile (128 or
+// 256; a 128-record tile uses half the threads to load and half a selection
+// chunk's frame).  Builds other than FW = 32, TJ = 256 with the default
+// occupancy are made only of the lean tile-relative kernel without the
+// potential (the autotuner's candidates).
+template <int MODE, bool POT, bool NEAR, bool SPLIT, bool LEAN, int FW = 32, int WPE = (SPLIT ? 4 : 3),
+          int TJ = kTile>
 __global__ void __launch_bounds__(kForceThreads) __attribute__((amdgpu_waves_per_eu(WPE)))
 force_kernel(DevState s, const int32_t* __restrict__ act, int par, int64_t target_items) {
   static_assert(FW == 16 || FW == 32 || FW == 64, "FP32 window of 16, 32 or 64 pairs");
+  static_assert(TJ == 128 || TJ == kTile, "j-tiles of 128 or 256 records");
   __shared__ __attribute__((aligned(16))) unsigned char lds[kLdsBytes];
   __shared__ float wmax[kTile / 16];
   __shared__ int64_t offs_sh[kLdsClusters];
@@ -912,9 +919,9 @@ force_kernel(DevState s, const int32_t* __restrict__ act, int par, int64_t targe
     const int64_t local = item - P.item_off;
     if constexpr (SPLIT) {
       switch (P.variant) {
-        case 2: run_item<SM, 4, 1, POT, SNEAR, false, FW>(s, act, P, c, local, lds, wmax); break;
-        case 3: run_item<SM, 16, 1, POT, SNEAR, false, FW>(s, act, P, c, local, lds, wmax); break;
-        case 4: run_item<SM, 64, 1, POT, SNEAR, false, FW>(s, act, P, c, local, lds, wmax); break;
+        case 2: run_item<SM, 4, 1, POT, SNEAR, false, FW, TJ>(s, act, P, c, local, lds, wmax); break;
+        case 3: run_item<SM, 16, 1, POT, SNEAR, false, FW, TJ>(s, act, P, c, local, lds, wmax); break;
+        case 4: run_item<SM, 64, 1, POT, SNEAR, false, FW, TJ>(s, act, P, c, local, lds, wmax); break;
         default:
           if (threadIdx.x == 0)
             __hip_atomic_fetch_or(s.status, (int32_t)ST_STATE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -926,18 +933,18 @@ force_kernel(DevState s, const int32_t* __restrict__ act, int par, int64_t targe
       // per launch): the host plans it with that layout's threshold above
       // any block size, so layout 0 never occurs here
       switch (P.variant) {
-        case 1: run_item<MODE, 1, 1, POT, NEAR, LEAN, FW>(s, act, P, c, local, lds, wmax); break;
-        case 2: run_item<SM, 4, 1, POT, SNEAR, false, FW>(s, act, P, c, local, lds, wmax); break;
-        case 3: run_item<SM, 16, 1, POT, SNEAR, false, FW>(s, act, P, c, local, lds, wmax); break;
-        default: run_item<SM, 64, 1, POT, SNEAR, false, FW>(s, act, P, c, local, lds, wmax); break;
+        case 1: run_item<MODE, 1, 1, POT, NEAR, LEAN, FW, TJ>(s, act, P, c, local, lds, wmax); break;
+        case 2: run_item<SM, 4, 1, POT, SNEAR, false, FW, TJ>(s, act, P, c, local, lds, wmax); break;
+        case 3: run_item<SM, 16, 1, POT, SNEAR, false, FW, TJ>(s, act, P, c, local, lds, wmax); break;
+        default: run_item<SM, 64, 1, POT, SNEAR, false, FW, TJ>(s, act, P, c, local, lds, wmax); break;
       }
     } else {
       switch (P.variant) {
-        case 0: run_item<MODE, 1, 2, POT, NEAR, LEAN, FW>(s, act, P, c, local, lds, wmax); break;
-        case 1: run_item<MODE, 1, 1, POT, NEAR, LEAN, FW>(s, act, P, c, local, lds, wmax); break;
-        case 2: run_item<SM, 4, 1, POT, SNEAR, false, FW>(s, act, P, c, local, lds, wmax); break;
-        case 3: run_item<SM, 16, 1, POT, SNEAR, false, FW>(s, act, P, c, local, lds, wmax); break;
-        default: run_item<SM, 64, 1, POT, SNEAR, false, FW>(s, act, P, c, local, lds, wmax); break;
+        case 0: run_item<MODE, 1, 2, POT, NEAR, LEAN, FW, TJ>(s, act, P, c, local, lds, wmax); break;
+        case 1: run_item<MODE, 1, 1, POT, NEAR, LEAN, FW, TJ>(s, act, P, c, local, lds, wmax); break;
+        case 2: run_item<SM, 4, 1, POT, SNEAR, false, FW, TJ>(s, act, P, c, local, lds, wmax); break;
+        case 3: run_item<SM, 16, 1, POT, SNEAR, false, FW, TJ>(s, act, P, c, local, lds, wmax); break;
+        default: run_item<SM, 64, 1, POT, SNEAR, false, FW, TJ>(s, act, P, c, local, lds, wmax); break;
       }
     }
     __syncthreads();  // LDS is reused by the next item
@@ -951,12 +958,15 @@ struct ForceLaunch {
   bool lean;
   int64_t target_items;
   hipStream_t st;
-  int window, waves;  // FP32 window and occupancy of the lean tile-relative kernel
+  int window, waves, tile;  // FP32 window, occupancy and j-tile of the lean tile-relative kernel
 };
 
 // The lean tile-relative kernel without the potential in one of the
 // autotuner's other builds (window 16, 32 or 64; 2 to 5 waves per SIMD;
-// not the default 32 / 4): force_tuned.hip.
+// j-tiles of 256 or 128 records, the latter with windows of 16 or 32; not
+// the default 32 / 4 / 256):
+// force_tuned.hip and force_tuned_t128.hip.
 hipError_t launch_force_tuned(const ForceLaunch& L);
+hipError_t launch_force_tuned_t128(const ForceLaunch& L);
 
 }  // namespace nb

@@ -1,8 +1,9 @@
 // The autotuner's other builds of the lean tile-relative force kernel
-// without the potential: FP32 window of 16, 32 or 64 pairs and an
-// occupancy of 2 to 5 waves per SIMD (the default, 32 and 4, is built
-// with the other kernels in force.hip).  Compiled on its own so that the
-// library's sources build in parallel.
+// without the potential on j-tiles of 256 records: FP32 window of 16, 32 or
+// 64 pairs and an occupancy of 2 to 5 waves per SIMD (the default, 32 and
+// 4, is built with the other kernels in force.hip; the 128-record tiles in
+// force_tuned_t128.hip).  Compiled on its own so that the library's sources
+// build in parallel.
 #include "force_impl.h"
 
 namespace nb {
@@ -14,6 +15,7 @@ static void launch_tr(const ForceLaunch& L) {
 }
 
 hipError_t launch_force_tuned(const ForceLaunch& L) {
+  if (L.tile == 128) return launch_force_tuned_t128(L);
   switch (L.window * 10 + L.waves) {
     case 162: launch_tr<16, 2>(L); break;
     case 163: launch_tr<16, 3>(L); break;

@@ -22,11 +22,12 @@ constexpr int kSelThreads = 256;
 // selection count and target_items), -1 for the plan in s.plan.  lean: the
 // tile-relative near build without the masked sweep (every cluster's
 // softening keeps the self pair finite in FP32; see force_impl.h).  window,
-// waves: FP32 window (16, 32, 64) and waves per SIMD (2 to 5) of the lean
-// tile-relative kernel without the potential; other kernels use 32 and
-// their own occupancy.
+// waves, tile: FP32 window (16, 32, 64), waves per SIMD (2 to 5) and
+// j-records per LDS tile (128 or 256) of the lean tile-relative kernel
+// without the potential; other kernels use 32, their own occupancy and 256.
 hipError_t launch_force(const DevState& s, int mode, bool pot, bool near, bool split, bool lean, const int32_t* act,
-                        int grid, int par, int64_t target_items, hipStream_t st, int window = 32, int waves = 4);
+                        int grid, int par, int64_t target_items, hipStream_t st, int window = 32, int waves = 4,
+                        int tile = 256);
 
 // Plan the force pass for the active offsets `aoff` (device, nc+1) of an
 // active list of at most n_act_bound entries.  target_items: work items aimed

@@ -111,7 +111,8 @@ class Tuning(ctypes.Structure):
         ("mid_tau", ctypes.c_double),
         ("window", ctypes.c_int32),
         ("waves", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 2),
+        ("tile", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 
@@ -342,7 +343,7 @@ class Sim:
                 "mixed_format": t.mixed_format, "rsq_bias_correct": t.rsq_bias_correct,
                 "near_tau": t.near_tau, "small_cluster_n": t.small_cluster_n,
                 "small_min_block": list(t.small_min_block), "near_tau_k": t.near_tau_k,
-                "mid_tau": t.mid_tau, "window": t.window, "waves": t.waves}
+                "mid_tau": t.mid_tau, "window": t.window, "waves": t.waves, "tile": t.tile}
 
     def set_tuning(self, **kw) -> None:
         cur = self.get_tuning()
@@ -359,6 +360,7 @@ class Sim:
         t.mid_tau = float(cur["mid_tau"])
         t.window = int(cur["window"])
         t.waves = int(cur["waves"])
+        t.tile = int(cur["tile"])
         t.small_cluster_n = int(cur["small_cluster_n"])
         for i in range(4):
             t.small_min_block[i] = int(cur["small_min_block"][i])

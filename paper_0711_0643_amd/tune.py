@@ -6,8 +6,9 @@ What is searched (all runtime knobs of the library):
     with 2 i per lane, 1 i per lane, 4, 16 lanes per i (min_block, applied
     to every cluster: small_cluster_n = 0), chosen by timing every layout at
     a ladder of block sizes;
-  * (mixed) the build of the lean tile-relative kernel: FP32 window of 16,
-    32 or 64 pairs and 2 to 5 waves per SIMD (window, waves), on the full
+  * (mixed) the build of the lean tile-relative kernel: j-tiles of 256 or
+    128 records, FP32 window of 16, 32 or 64 pairs (16 or 32 on 128-record
+    tiles) and 2 to 5 waves per SIMD (tile, window, waves), on the full
     block, among the builds no slower than the default on the smallest
     block (a build that spills registers costs microseconds per launch);
   * the j-slicing target (target_items) and the persistent grid size (grid)
@@ -47,6 +48,15 @@ import numpy as np
 BIG = 1 << 30
 GATE_MIXED = 1e-6
 GATE_MIXED_JERK_MAX = 1e-4
+
+# the builds of the lean tile-relative kernel (force_tuned.hip, force_tuned_t128.hip)
+BUILDS = [dict(tile=tile, window=window, waves=waves)
+          for tile in (256, 128) for window in (16, 32, 64) for waves in (2, 3, 4, 5)
+          if not (tile == 128 and window == 64)]
+
+
+def _key(cfg):
+    return (cfg["tile"], cfg["window"], cfg["waves"])
 GATE_FP64 = 1e-12
 
 
@@ -218,18 +228,15 @@ def tune(sim, use_cache: bool = True, ladder=None, verbose: bool = False) -> dic
         small_act, small_aoff = active(ladder[0])
         small_ref = reference(small_act, small_aoff)
         t_small = {}
-        for window in (16, 32, 64):
-            for waves in (2, 3, 4, 5):
-                cfg = dict(tuned, window=window, waves=waves)
-                t_small[(window, waves)] = trial(cfg, small_act, small_aoff, small_ref, n_act=ladder[0],
-                                                 window=window, waves=waves)
-        limit = 1.05 * t_small[(base["window"], base["waves"])]
-        for window in (16, 32, 64):
-            for waves in (2, 3, 4, 5):
-                cfg = dict(tuned, window=window, waves=waves)
-                ms = trial(cfg, act, aoff, ref, n_act=n, window=window, waves=waves)
-                if t_small[(window, waves)] <= limit and (best is None or ms < best[0]):
-                    best = (ms, cfg)
+        for build in BUILDS:
+            cfg = dict(tuned, **build)
+            t_small[_key(build)] = trial(cfg, small_act, small_aoff, small_ref, n_act=ladder[0], **build)
+        limit = 1.05 * t_small[_key(base)]
+        for build in BUILDS:
+            cfg = dict(tuned, **build)
+            ms = trial(cfg, act, aoff, ref, n_act=n, **build)
+            if t_small[_key(build)] <= limit and (best is None or ms < best[0]):
+                best = (ms, cfg)
         if best is not None:
             tuned = best[1]
     best = None

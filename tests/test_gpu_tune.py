@@ -50,8 +50,8 @@ def test_tuner_picks_a_parity_passing_config(precision, tmp_path, monkeypatch):
     assert all({"err", "err_jerk_p999", "err_pot", "ok"} <= set(r) for r in recs)
     if precision == 1:
         if min(cfg["min_block"][:2]) <= n:  # the full block runs a one-lane-per-i layout: builds searched
-            assert {(r["window"], r["waves"]) for r in recs if "window" in r} == {
-                (w, q) for w in (16, 32, 64) for q in (2, 3, 4, 5)}
+            assert {(r["tile"], r["window"], r["waves"]) for r in recs if "window" in r} == {
+                tune._key(b) for b in tune.BUILDS}
     # a second call is served from the cache
     sim2 = nb.Sim(m, x, v, eps, precision=precision)
     assert tune.tune(sim2) == cfg
@@ -98,10 +98,11 @@ def test_batch_tuner_restores_state_and_passes_parity(tmp_path, monkeypatch):
     sim.close()
 
 
-@pytest.mark.parametrize("window", [16, 32, 64])
-def test_every_kernel_build_matches_oracle(window):
+@pytest.mark.parametrize("tile,window", [(256, 16), (256, 32), (256, 64), (128, 16), (128, 32)])
+def test_every_kernel_build_matches_oracle(tile, window):
     """Each build of the lean tile-relative kernel the tuner may choose
-    (FP32 window 16, 32, 64; 2 to 5 waves per SIMD) against the oracle:
+    (j-tiles of 256 or 128 records; FP32 window 16, 32, 64, or 16, 32 on
+    128-record tiles; 2 to 5 waves per SIMD) against the oracle:
     acceleration per particle, jerk per particle where kappa_k <= 10."""
     import torch
 
@@ -116,8 +117,8 @@ def test_every_kernel_build_matches_oracle(window):
         ra, rk, _ = oracle.force(m, x, v, eps, act)
         kappa = oracle.force_abs(m, x, v, eps, act)[1] / np.linalg.norm(rk, axis=0)
         for waves in (2, 3, 4, 5):
-            banner(f"kernel build window={window} waves={waves} n_act={na}")
-            sim.set_tuning(window=window, waves=waves, small_cluster_n=0)
+            banner(f"kernel build tile={tile} window={window} waves={waves} n_act={na}")
+            sim.set_tuning(tile=tile, window=window, waves=waves, small_cluster_n=0)
             a, k, _ = sim.force(act)
             torch.cuda.synchronize()
             assert sim.status() == 0
