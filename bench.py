@@ -316,6 +316,25 @@ def run_workload(name, args):
     print(json.dumps(out), flush=True)
 
 
+def fit_step_model(rows):
+    """Least-squares fit of T_adv(s) = tau_0 + tau_pr N + tau_cr s + tau_f N s
+    to measured block steps, rows of (N, s, seconds); relative residuals, so
+    that every step counts by its relative misfit.  Returns (tau_0, tau_pr,
+    tau_cr, tau_f)."""
+    A = np.array([[1.0, n, s_, n * s_] for n, s_, _ in rows])
+    y = np.array([t_ for _, _, t_ in rows])
+    w = 1.0 / y
+    coef, *_ = np.linalg.lstsq(A * w[:, None], y * w, rcond=None)
+    return tuple(float(c) for c in coef)
+
+
+def model_total(taus, n, mean_block, steps):
+    """Eq. tsnb on one GPU: the time of a run of `steps` block steps of mean
+    size `mean_block` in a system of n, T_N = T_adv(s_mean) n_steps."""
+    tau0, tau_pr, tau_cr, tau_f = taus
+    return (tau0 + tau_pr * n + tau_cr * mean_block + tau_f * n * mean_block) * steps
+
+
 def perf_model():
     """The paper's performance model on one MI355X (Sect. 4.1, Eq. tsnb).
 
@@ -359,15 +378,9 @@ def perf_model():
         per_n[n] = {"steps": int(times.size), "mean_block": float(sizes.mean()), "measured_s": float(times.sum())}
         for tt_, ss in zip(times, sizes):
             rows.append((n, ss, tt_))
-    A = np.array([[1.0, n, s_, n * s_] for n, s_, _ in rows])
-    y = np.array([t_ for _, _, t_ in rows])
-    # relative least squares: every step counts by its relative misfit
-    w = 1.0 / y
-    coef, *_ = np.linalg.lstsq(A * w[:, None], y * w, rcond=None)
-    tau0, tau_pr, tau_cr, tau_f = (float(c) for c in coef)
+    tau0, tau_pr, tau_cr, tau_f = fit_step_model(rows)
     for n, rec in per_n.items():
-        t_adv = tau0 + tau_pr * n + tau_cr * rec["mean_block"] + tau_f * n * rec["mean_block"]
-        rec["model_s"] = t_adv * rec["steps"]
+        rec["model_s"] = model_total((tau0, tau_pr, tau_cr, tau_f), n, rec["mean_block"], rec["steps"])
         rec["model_over_measured"] = rec["model_s"] / rec["measured_s"]
     return {"fit": {"tau_0_s": tau0, "tau_pr_s": tau_pr, "tau_cr_s": tau_cr, "tau_f_s": tau_f,
                     "interactions_per_s_from_tau_f": 1.0 / tau_f if tau_f > 0 else None},
