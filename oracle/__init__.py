@@ -67,6 +67,8 @@ def lib() -> ctypes.CDLL:
         L.oracle_force_sliced.restype = None
         L.oracle_force_abs.argtypes = [i64, p, p, p, f64, i64, p, p]
         L.oracle_force_abs.restype = None
+        L.oracle_perturbers.argtypes = [i64, p, p, f64, f64, i64, p, ctypes.c_int32, p, p]
+        L.oracle_perturbers.restype = None
         L.oracle_predict.argtypes = [i64, p, p, p, p, p, f64, p, p]
         L.oracle_predict.restype = None
         L.oracle_correct_one.argtypes = [f64, p, p, p, p, p, p, p, p, p, p]
@@ -147,6 +149,22 @@ def force_abs(m, x, v, eps: float, active=None) -> np.ndarray:
     out = np.zeros((3, act.shape[0]))
     lib().oracle_force_abs(n, _ptr(m), _ptr(x), _ptr(v), float(eps), act.shape[0], _ptr(act), _ptr(out))
     return out
+
+
+def perturbers(m, x, eps: float, thr: float, active=None, cap: int = 256):
+    """Perturber lists (Sect. 3.1): for each active i the j != i with
+    m_j / (|x_j - x_i|^2 + eps^2) > thr, in ascending j, at most ``cap`` of
+    them.  Returns ``(lists, counts)``: lists (n_act, cap) int32 padded with
+    -1, counts (n_act,) the number of j that pass (also beyond cap)."""
+    m, x = _f64(m), _f64(x)
+    n = m.shape[0]
+    act = np.arange(n, dtype=np.int32) if active is None else np.ascontiguousarray(active, dtype=np.int32)
+    na = act.shape[0]
+    lists = np.empty((na, cap), dtype=np.int32)
+    counts = np.empty(na, dtype=np.int32)
+    lib().oracle_perturbers(n, _ptr(m), _ptr(x), float(eps), float(thr), na, _ptr(act), int(cap), _ptr(lists),
+                            _ptr(counts))
+    return lists, counts
 
 
 def predict(x, v, a, k, t, t_pred: float):

@@ -164,6 +164,37 @@ void oracle_force_abs(int64_t n, const double *m, const double *x, const double 
 }
 
 /* ---------------------------------------------------------------------- */
+/* Perturber lists (Sect. 3.1): for each star the stars whose force on it  */
+/* exceeds a threshold, in the order a serial sweep over the particles    */
+/* identifies them, at most cap of them (the paper's code keeps 256).     */
+
+/* For active particle i = act[q]: every j != i with
+ * m_j / (|x_j - x_i|^2 + eps^2) > thr, in ascending j, the first cap of them
+ * in lists[q * cap ...] and -1 in the rest of the row; counts[q] = the
+ * number of j that pass, also beyond cap.  R^2 is formed as
+ * ((dx dx + dy dy) + dz dz) + eps^2, each operation rounded. */
+void oracle_perturbers(int64_t n, const double *m, const double *x, double eps, double thr, int64_t n_act,
+                       const int32_t *act, int32_t cap, int32_t *lists, int32_t *counts) {
+    const double eps2 = eps * eps;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t q = 0; q < n_act; ++q) {
+        const int64_t i = act[q];
+        int32_t found = 0;
+        for (int32_t s = 0; s < cap; ++s) lists[q * cap + s] = -1;
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            const double dx = x[j] - x[i], dy = x[n + j] - x[n + i], dz = x[2 * n + j] - x[2 * n + i];
+            const double r2 = dx * dx + dy * dy + dz * dz + eps2;
+            if (m[j] / r2 > thr) {
+                if (found < cap) lists[q * cap + found] = (int32_t)j;
+                ++found;
+            }
+        }
+        counts[q] = found;
+    }
+}
+
+/* ---------------------------------------------------------------------- */
 /* Hermite predictor (Sect. 2.1, predictor equations).                    */
 
 void oracle_predict(int64_t n, const double *x, const double *v, const double *a,

@@ -514,6 +514,65 @@ def pin_plummer_energy_conservation():
     assert np.all(np.fmod(sim.t, sim.dt) == 0.0)
 
 
+def pin_perturbers_lattice_closed_form():
+    """Perturber lists (Sect. 3.1) on a line of equal masses m at integer
+    positions, ids permuted against positions, eps = 0 and threshold m / 9:
+    a star's perturbers are the stars one or two places away (m/1, m/4 pass,
+    m/9 equals the threshold and does not), listed by ascending id (the
+    order a serial sweep finds them), not by position."""
+    n, mm = 40, 0.025
+    rng = np.random.default_rng(5)
+    place = rng.permutation(n)  # id -> position on the line
+    x = np.zeros((3, n))
+    x[0] = place.astype(float)
+    m = np.full(n, mm)
+    lists, counts = oracle.perturbers(m, x, 0.0, mm / 9.0, cap=8)
+    for i in range(n):
+        want = sorted(j for j in range(n) if j != i and abs(int(place[j]) - int(place[i])) <= 2)
+        assert counts[i] == len(want), (i, counts[i], want)
+        assert list(lists[i, :len(want)]) == want, (i, lists[i], want)
+        assert np.all(lists[i, len(want):] == -1)
+
+
+def pin_perturbers_cap_keeps_first_in_id_order():
+    """With every other star passing (threshold 0), the list holds the first
+    cap ids in ascending order (skipping the star itself) and the count all
+    n - 1 of them."""
+    n, cap = 300, 256
+    rng = np.random.default_rng(6)
+    x = rng.standard_normal((3, n))
+    m = np.full(n, 1.0 / n)
+    act = np.array([0, 7, 299], dtype=np.int32)
+    lists, counts = oracle.perturbers(m, x, 0.01, 0.0, active=act, cap=cap)
+    for q, i in enumerate(act):
+        want = [j for j in range(n) if j != i][:cap]
+        assert counts[q] == n - 1
+        assert list(lists[q]) == want
+
+
+def pin_perturbers_mass_not_distance():
+    """A heavy star far away passes where a light near one does not (the
+    force, not the distance, decides): m = 1e-3 at R = 0.1 gives 0.1, m = 10
+    at R = 5 gives 0.4, threshold 0.2."""
+    m = np.array([1.0, 1e-3, 10.0])
+    x = np.zeros((3, 3))
+    x[0] = [0.0, 0.1, 5.0]
+    lists, counts = oracle.perturbers(m, x, 0.0, 0.2, active=np.array([0], dtype=np.int32), cap=4)
+    assert counts[0] == 1 and list(lists[0]) == [2, -1, -1, -1]
+
+
+def pin_perturbers_softened_distance():
+    """Plummer softening enters the test as in the force: m / (R^2 + eps^2).
+    Two stars at R = 1, m = 1, threshold 0.9: they perturb each other with
+    eps = 0 (1 > 0.9) and not with eps = 0.5 (1 / 1.25 = 0.8)."""
+    m = np.ones(2)
+    x = np.zeros((3, 2))
+    x[1, 1] = 1.0
+    _, c0 = oracle.perturbers(m, x, 0.0, 0.9, cap=2)
+    _, c1 = oracle.perturbers(m, x, 0.5, 0.9, cap=2)
+    assert list(c0) == [1, 1] and list(c1) == [0, 0]
+
+
 ALL_PINS = [
     pin_two_body_closed_form,
     pin_cube_closed_form,
@@ -527,6 +586,10 @@ ALL_PINS = [
     pin_force_abs_rotating_ring,
     pin_force_abs_collinear_equality,
     pin_force_abs_bounds,
+    pin_perturbers_lattice_closed_form,
+    pin_perturbers_cap_keeps_first_in_id_order,
+    pin_perturbers_mass_not_distance,
+    pin_perturbers_softened_distance,
     pin_diagnostics_galilean_boost,
     pin_diagnostics_two_body_closed_form,
     pin_boosted_kepler_momentum,

@@ -46,6 +46,15 @@ MUTANTS = {
     "diag_momentum_index": ("p[d] += m[i] * vi[d];", "p[d] += m[i] * vi[0];"),
     "diag_angmom_sign": ("l[2] += m[i] * (xi[0] * vi[1] - xi[1] * vi[0]);", "l[2] += m[i] * (xi[1] * vi[0] - xi[0] * vi[1]);"),
     "diag_kinetic_half": ("ke += 0.5 * m[i] *", "ke += m[i] *"),
+    "pert_not_strict": ("if (m[j] / r2 > thr) {", "if (m[j] / r2 >= thr) {"),
+    "pert_self_term": ("        int32_t found = 0;\n        for (int32_t s = 0; s < cap; ++s) lists[q * cap + s] = -1;\n        for (int64_t j = 0; j < n; ++j) {\n            if (j == i) continue;",
+                       "        int32_t found = 0;\n        for (int32_t s = 0; s < cap; ++s) lists[q * cap + s] = -1;\n        for (int64_t j = 0; j < n; ++j) {"),
+    "pert_no_softening": ("const double r2 = dx * dx + dy * dy + dz * dz + eps2;\n            if (m[j] / r2 > thr)",
+                          "const double r2 = dx * dx + dy * dy + dz * dz;\n            if (m[j] / r2 > thr)"),
+    "pert_mass_of_i": ("if (m[j] / r2 > thr) {", "if (m[i] / r2 > thr) {"),
+    "pert_descending": ("        for (int64_t j = 0; j < n; ++j) {\n            if (j == i) continue;\n            const double dx = x[j] - x[i], dy = x[n + j] - x[n + i], dz = x[2 * n + j] - x[2 * n + i];\n            const double r2 = dx * dx + dy * dy + dz * dz + eps2;\n            if (m[j] / r2 > thr)",
+                        "        for (int64_t j = n - 1; j >= 0; --j) {\n            if (j == i) continue;\n            const double dx = x[j] - x[i], dy = x[n + j] - x[n + i], dz = x[2 * n + j] - x[2 * n + i];\n            const double r2 = dx * dx + dy * dy + dz * dz + eps2;\n            if (m[j] / r2 > thr)"),
+    "pert_cap_short": ("if (found < cap) lists[q * cap + found] = (int32_t)j;", "if (found < cap - 1) lists[q * cap + found] = (int32_t)j;"),
 }
 
 CHILD = r"""
