@@ -173,6 +173,28 @@ NBODY_API nbody_status nbody_force_noalloc(nbody_ctx *ctx, const int32_t *active
                                  const int64_t *active_offsets, int64_t n_active, double *acc,
                                  double *jerk, double *pot);
 
+/* Perturber lists (Sect. 3.1): for each listed particle i, the particles
+ * j != i of its cluster whose force on i exceeds the cluster's threshold,
+ * m_j / (|x_j - x_i|^2 + eps^2) > threshold[c] on the predicted positions
+ * (the state nbody_force would use), in ascending particle id -- the order
+ * in which a serial sweep over the particles identifies them, which keeps
+ * the lists identical to a serial code's -- at most max_pert of them.  R^2
+ * is formed as ((dx dx + dy dy) + dz dz) + eps^2 in FP64, each operation
+ * rounded, so the lists are reproducible bit for bit.
+ *   active_idx, active_offsets, n_active: as for nbody_force.
+ *   threshold: device, n_clusters doubles (e.g. a small fraction of the
+ *              cluster's mean |a|).
+ *   max_pert: 1 .. 256 (the paper's codes keep 256).
+ *   lists: device, [n_active][max_pert] int32: the ids, then -1.
+ *   counts: device, [n_active] int32: how many j pass (may exceed max_pert).
+ * Asynchronous on the library's stream.  NBODY_E_INVAL for bad sizes or
+ * NULL pointers; an id outside its cluster is reported as NBODY_E_INDEX
+ * (device) and gets an empty list. */
+NBODY_API nbody_status nbody_perturbers(nbody_ctx *ctx, const int32_t *active_idx,
+                              const int64_t *active_offsets, int64_t n_active,
+                              const double *threshold, int32_t max_pert, int32_t *lists,
+                              int32_t *counts);
+
 /* Hermite corrector, Aarseth step and block quantisation (Sect. 2.1) for the
  * listed particles, advancing each to its cluster's last predicted time
  * (the prediction time of nbody_predict, or of the last block step).

@@ -10,7 +10,7 @@ PKG = Path(__file__).resolve().parent
 ROOT = PKG.parent
 CSRC = PKG / "csrc"
 LIB = PKG / "libnbody.so"
-SOURCES = ["force.hip", "force_tuned.hip", "force_tuned_t128.hip", "step.hip", "api.hip"]
+SOURCES = ["force.hip", "force_tuned.hip", "force_tuned_t128.hip", "step.hip", "perturbers.hip", "api.hip"]
 BUILD = PKG / "_build"
 
 HIPCC_FLAGS = [

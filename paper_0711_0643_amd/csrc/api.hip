@@ -61,7 +61,8 @@ constexpr uint32_t kStateVersion = 2;
 struct Layout {
   size_t coff, eps, cid, ch_cluster, ch_begin, cl_ch, order, slot_of, tmeta, ulist;
   size_t m, x, v, a, k, t, dt, xp, vp, pot, jr;
-  size_t tpred, tnow, inter, steps, cm2, cm2n, acount, umin, ucnt, act, aoff, plan, offs, ctl, part, fout, status, eout;
+  size_t tpred, tnow, inter, steps, cm2, cm2n, acount, umin, ucnt, act, aoff, plan, offs, ctl, part, fout, pid, status,
+      eout;
   size_t total;
   int64_t rows_cap;
   int64_t nch_max;
@@ -117,6 +118,7 @@ Layout make_layout(int64_t n, int32_t nc) {
   L.ctl = take(sizeof(Ctl));
   L.part = take(8 * 7 * (size_t)L.rows_cap);
   L.fout = take(8 * 7 * N);
+  L.pid = take(8 * 4 * N);
   L.status = take(4);
   L.eout = take(64 * C);
   L.total = o;
@@ -241,6 +243,9 @@ namespace {
   do {                                        \
     if ((expr) != hipSuccess) return NBODY_E_HIP; \
   } while (0)
+
+// Longest perturber list (Sect. 3.1: the paper's codes keep 256).
+constexpr int32_t kMaxPerturbers = 256;
 
 int force_mode(const nbody_ctx* c) { return c->p.precision == NBODY_FP64 ? kF64 : c->mixed_mode; }
 
@@ -520,6 +525,7 @@ nbody_status nbody_init(nbody_ctx** out, int64_t n_total, int32_t n_clusters, co
   s.part = (double*)(w + L.part);
   s.rows_cap = L.rows_cap;
   s.fout = (double*)(w + L.fout);
+  s.pid = (double*)(w + L.pid);
   s.status = (int32_t*)(w + L.status);
 
   c->ctl.vmin[0] = 1 << 30;  // two i per lane: off (one i per lane is faster on gfx950)
@@ -690,6 +696,20 @@ nbody_status nbody_force_noalloc(nbody_ctx* c, const int32_t* active_idx, const 
   s.part = c->scratch;  // every row a pass reads is written by that pass first: nothing to clear
   s.rows_cap = kScratchRows;
   return force_pass(c, s, active_idx, active_offsets, n_active, acc, jerk, pot, false);
+}
+
+nbody_status nbody_perturbers(nbody_ctx* c, const int32_t* active_idx, const int64_t* active_offsets,
+                              int64_t n_active, const double* threshold, int32_t max_pert, int32_t* lists,
+                              int32_t* counts) {
+  if (!c || n_active < 0 || n_active > c->n || max_pert < 1 || max_pert > kMaxPerturbers) return NBODY_E_INVAL;
+  if (n_active == 0) return NBODY_OK;
+  if (!active_idx || !active_offsets || !threshold || !lists || !counts) return NBODY_E_INVAL;
+  if (!c->predicted) return NBODY_E_STATE;
+  const nbody_status r = complete_prediction(c);
+  if (r != NBODY_OK) return r;
+  HIP_OK(launch_perturbers(c->s, active_idx, active_offsets, n_active, threshold, max_pert, lists, counts,
+                           c->stream));
+  return NBODY_OK;
 }
 
 nbody_status nbody_correct(nbody_ctx* c, const int32_t* active_idx, const int64_t* active_offsets, int64_t n_active,

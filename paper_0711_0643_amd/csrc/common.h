@@ -153,6 +153,7 @@ struct DevState {
   double* part;    // [7][rows_cap] partial sums
   int64_t rows_cap;
   double* fout;    // [7][n] reduced force of internal passes (a, k, pot)
+  double* pid;     // [4][n] perturber pass: predicted x, y, z and mass in particle-id order
   int32_t* status;
 };
 

@@ -53,6 +53,15 @@ hipError_t launch_reduce(const DevState& s, const int64_t* aoff, int64_t n_activ
 hipError_t launch_reduce_correct_step(const DevState& s, bool pot, int par, int64_t target_items, bool counting,
                                       hipStream_t st);
 
+// Perturber lists (perturbers.hip): for each entry q of the caller's
+// active list (particle ids, cluster c's entries at aoff[c] .. aoff[c+1]),
+// the ids j != i of its cluster with m_j / (|x_p,j - x_p,i|^2 + eps_c^2) >
+// thr[c] in ascending order, the first cap of them in lists[q * cap ...]
+// (-1 past the end) and their number in counts[q].  An id outside its
+// cluster sets ST_INDEX and gets an empty list.
+hipError_t launch_perturbers(const DevState& s, const int32_t* ids, const int64_t* aoff, int64_t n_active,
+                             const double* thr, int32_t cap, int32_t* lists, int32_t* counts, hipStream_t st);
+
 // Predict every particle of every cluster to s.tpred[c] (FP64 x_p, v_p,
 // every field of the mixed j-records and the tile frames).
 hipError_t launch_predict_all(const DevState& s, hipStream_t st);

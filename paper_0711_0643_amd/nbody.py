@@ -38,6 +38,7 @@ EXPORTED = [
     "nbody_predict",
     "nbody_force",
     "nbody_force_noalloc",
+    "nbody_perturbers",
     "nbody_correct",
     "nbody_step",
     "nbody_sync",
@@ -150,6 +151,8 @@ def lib() -> ctypes.CDLL:
         L.nbody_force.restype = st
         L.nbody_force_noalloc.argtypes = [p, p, p, i64, p, p, p]
         L.nbody_force_noalloc.restype = st
+        L.nbody_perturbers.argtypes = [p, p, p, i64, p, ctypes.c_int32, p, p]
+        L.nbody_perturbers.restype = st
         L.nbody_correct.argtypes = [p, p, p, i64, p, p]
         L.nbody_correct.restype = st
         L.nbody_step.argtypes = [p, i32, f64]
@@ -418,6 +421,23 @@ class Sim:
                                      ph.data_ptr() if ph is not None else None), entry)
         self._keep = (act, aoff)  # alive until the stream has consumed them
         return acc, jerk, ph
+
+    def perturbers(self, active_idx, threshold, active_offsets=None, max_pert: int = 256):
+        """Perturber lists (nbody_perturbers): threshold per cluster (sequence
+        or tensor of n_clusters floats); returns lists (n_act, max_pert) and
+        counts (n_act,) int32 tensors on the device."""
+        torch = self._torch
+        act, aoff = self._active(active_idx, active_offsets)
+        na = act.numel()
+        thr = torch.as_tensor(threshold, dtype=torch.float64).reshape(-1).to(self.device).contiguous()
+        if thr.numel() != self.nc:
+            raise ValueError("threshold needs one value per cluster")
+        lists = torch.empty((na, max_pert), dtype=torch.int32, device=self.device)
+        counts = torch.empty((na,), dtype=torch.int32, device=self.device)
+        _check(lib().nbody_perturbers(self._ctx, act.data_ptr(), aoff.data_ptr(), na, thr.data_ptr(), int(max_pert),
+                                      lists.data_ptr(), counts.data_ptr()), "nbody_perturbers")
+        self._keep = (act, aoff, thr)  # alive until the stream has consumed them
+        return lists, counts
 
     def correct(self, active_idx, acc, jerk, active_offsets=None) -> None:
         act, aoff = self._active(active_idx, active_offsets)
