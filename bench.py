@@ -655,6 +655,9 @@ def main():
             "force_sweep": fp["sweep"],
         },
         "mixed_force_sweep": mx["sweep"],
+        "force_sweep_note": ("a force call whose active list is below the one-lane-per-i threshold (1024) launches "
+                             "the same j-split FP64 kernel in both precisions (bitwise equal results); the two "
+                             "sweeps there differ by run-to-run noise only"),
         "mixed_alternatives": alt,
         "mixed_vs_fp64_error": {
             "acc_max_rel": float(ea.max()),
