@@ -4,8 +4,9 @@
 // identifies them (ascending particle id), at most max_pert of them.  The
 // paper broadcasts every processor's candidates and sorts them into that
 // order; here the predicted positions and masses are first staged in id
-// order, then one wavefront sweeps the whole cluster for its i in id order
-// and compacts the passing ids in place, so the order comes out directly.
+// order, then each listed i sweeps its whole cluster in id order (through
+// LDS tiles shared by a group of i's) and places the passing ids in order as
+// they are found, so the order comes out directly.
 // The test m_j / R^2 > threshold is taken in FP64 with R^2 formed as
 // ((dx dx + dy dy) + dz dz) + eps^2, every operation rounded (no fused
 // multiply-add), so a list is the same bit for bit on any machine that
@@ -17,7 +18,8 @@ namespace nb {
 namespace {
 
 constexpr int kPertThreads = 256;
-constexpr int kPertPer = 4;  // consecutive ids per lane per round
+constexpr int kPertGroup = 16;    // listed particles per workgroup
+constexpr int kPertRound = 1024;  // j-ids per LDS round
 
 __device__ __forceinline__ double softened_r2(double dx, double dy, double dz, double eps2) {
 #pragma clang fp contract(off)
@@ -37,70 +39,102 @@ __global__ void __launch_bounds__(256) stage_by_id_kernel(DevState s) {
   }
 }
 
-// One wavefront per active entry q (grid-stride over entries, four per
-// workgroup).  Each round covers 64 * kPertPer consecutive ids, lane l the
-// kPertPer ids from l * kPertPer on; an exclusive scan of the lanes' pass
-// counts (shuffles only: no barrier, no LDS) gives every passing id its
-// place, so the list fills in ascending order.
+// One workgroup per group of kPertGroup consecutive entries (grid-stride),
+// taken cluster by cluster (entries are cluster-major, so a group meets few
+// clusters); each wavefront holds kPertGroup / 4 of them.  The cluster's
+// id-ordered j-data pass through LDS in rounds of kPertRound ids, read by
+// every entry of the group.  Lane l tests ids u * 64 + l of the round
+// (consecutive lanes, consecutive LDS words), and a ballot per u places the
+// passing ids in ascending order.
 __global__ void __launch_bounds__(kPertThreads)
 perturbers_kernel(DevState s, const int32_t* __restrict__ ids, const int64_t* __restrict__ aoff, int64_t n_active,
                   const double* __restrict__ thr, int32_t cap, int32_t* __restrict__ lists,
                   int32_t* __restrict__ counts) {
   constexpr int kWaves = kPertThreads / 64;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  constexpr int kPerWave = kPertGroup / kWaves;
+  __shared__ double tX[kPertRound], tY[kPertRound], tZ[kPertRound], tM[kPertRound];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const uint64_t below = (1ull << lane) - 1ull;
   const int64_t n = s.n;
   const double* X = s.pid;
   const double* Y = s.pid + n;
   const double* Z = s.pid + 2 * n;
   const double* M = s.pid + 3 * n;
-  for (int64_t q = (int64_t)blockIdx.x * kWaves + wave; q < n_active; q += (int64_t)gridDim.x * kWaves) {
-    // cluster of entry q: the last c with aoff[c] <= q
-    int lo = 0, hi = s.nc - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (aoff[mid] <= q) lo = mid; else hi = mid - 1;
-    }
-    const int c = lo;
-    const int64_t b = s.coff[c], e = s.coff[c + 1];
-    const int64_t id = ids[q];
-    int32_t found = 0;
-    if (id >= b && id < e) {
-      const double xi = X[id], yi = Y[id], zi = Z[id];
+  for (int64_t g0 = (int64_t)blockIdx.x * kPertGroup; g0 < n_active; g0 += (int64_t)gridDim.x * kPertGroup) {
+    const int64_t g1 = g0 + kPertGroup < n_active ? g0 + kPertGroup : n_active;
+    for (int64_t qs = g0; qs < g1;) {  // the clusters met by the group, in order (uniform)
+      int lo = 0, hi = s.nc - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (aoff[mid] <= qs) lo = mid; else hi = mid - 1;
+      }
+      const int c = lo;
+      const int64_t b = s.coff[c], e = s.coff[c + 1];
+      const int64_t qe = aoff[c + 1] < g1 ? aoff[c + 1] : g1;
       const double eps2 = s.eps[c] * s.eps[c];
       const double t = thr[c];
-      for (int64_t j0 = b; j0 < e; j0 += 64 * kPertPer) {
-        const int64_t jb = j0 + (int64_t)lane * kPertPer;
-        unsigned bits = 0;
+      // this wavefront's entries of the cluster
+      int64_t q[kPerWave], id[kPerWave];
+      bool on[kPerWave];
+      double xi[kPerWave], yi[kPerWave], zi[kPerWave];
+      int32_t found[kPerWave];
 #pragma unroll
-        for (int u = 0; u < kPertPer; ++u) {
-          const int64_t j = jb + u;
-          if (j < e && j != id) {
-            const double r2 = softened_r2(X[j] - xi, Y[j] - yi, Z[j] - zi, eps2);
-            if (M[j] / r2 > t) bits |= 1u << u;
+      for (int k = 0; k < kPerWave; ++k) {
+        q[k] = qs + wave * kPerWave + k;
+        id[k] = -1;
+        on[k] = false;
+        xi[k] = yi[k] = zi[k] = 0.0;
+        found[k] = 0;
+        if (q[k] < qe) {
+          id[k] = ids[q[k]];
+          on[k] = id[k] >= b && id[k] < e;
+          if (on[k]) {
+            xi[k] = X[id[k]];
+            yi[k] = Y[id[k]];
+            zi[k] = Z[id[k]];
+          } else if (lane == 0) {
+            __hip_atomic_fetch_or(s.status, (int32_t)ST_INDEX, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           }
         }
-        const int cnt = __popc(bits);
-        int incl = cnt;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-          const int up = __shfl_up(incl, o);
-          if (lane >= o) incl += up;
-        }
-        int at = found + incl - cnt;
-#pragma unroll
-        for (int u = 0; u < kPertPer; ++u) {
-          if ((bits >> u) & 1u) {
-            if (at < cap) lists[q * cap + at] = (int32_t)(jb + u);
-            ++at;
-          }
-        }
-        found += __shfl(incl, 63);
       }
-    } else if (lane == 0) {
-      __hip_atomic_fetch_or(s.status, (int32_t)ST_INDEX, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      for (int64_t j0 = b; j0 < e; j0 += kPertRound) {
+        __syncthreads();  // the previous round is consumed
+        for (int k = tid; k < kPertRound; k += kPertThreads) {
+          const int64_t j = j0 + k;
+          const bool in = j < e;
+          tX[k] = in ? X[j] : 0.0;
+          tY[k] = in ? Y[j] : 0.0;
+          tZ[k] = in ? Z[j] : 0.0;
+          tM[k] = in ? M[j] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kPerWave; ++k) {
+          if (!on[k]) continue;  // uniform within the wavefront
+          for (int u = 0; u < kPertRound / 64; ++u) {
+            const int l = u * 64 + lane;
+            const int64_t j = j0 + l;
+            bool pass = false;
+            if (j < e && j != id[k]) {
+              const double r2 = softened_r2(tX[l] - xi[k], tY[l] - yi[k], tZ[l] - zi[k], eps2);
+              pass = tM[l] / r2 > t;
+            }
+            const uint64_t mask = __ballot(pass);
+            const int at = found[k] + __popcll(mask & below);
+            if (pass && at < cap) lists[q[k] * cap + at] = (int32_t)j;
+            found[k] += __popcll(mask);
+          }
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < kPerWave; ++k) {
+        if (q[k] < qe) {
+          for (int m = (found[k] < cap ? found[k] : cap) + lane; m < cap; m += 64) lists[q[k] * cap + m] = -1;
+          if (lane == 0) counts[q[k]] = found[k];
+        }
+      }
+      qs = qe;
     }
-    for (int k = (found < cap ? found : cap) + lane; k < cap; k += 64) lists[q * cap + k] = -1;
-    if (lane == 0) counts[q] = found;
   }
 }
 
@@ -110,7 +144,7 @@ hipError_t launch_perturbers(const DevState& s, const int32_t* ids, const int64_
                              const double* thr, int32_t cap, int32_t* lists, int32_t* counts, hipStream_t st) {
   const int64_t sg = (s.n + 255) / 256;
   hipLaunchKernelGGL(stage_by_id_kernel, dim3((unsigned)(sg < 65536 ? sg : 65536)), dim3(256), 0, st, s);
-  const int64_t wgs = (n_active + kPertThreads / 64 - 1) / (kPertThreads / 64);
+  const int64_t wgs = (n_active + kPertGroup - 1) / kPertGroup;
   const int64_t grid = wgs < 65536 ? wgs : 65536;
   hipLaunchKernelGGL(perturbers_kernel, dim3((unsigned)grid), dim3(kPertThreads), 0, st, s, ids, aoff, n_active, thr,
                      cap, lists, counts);
