@@ -71,6 +71,15 @@ perturbers_kernel(DevState s, const int32_t* __restrict__ ids, const int64_t* __
       const int c = lo;
       const int64_t b = s.coff[c], e = s.coff[c + 1];
       const int64_t qe = aoff[c + 1] < g1 ? aoff[c + 1] : g1;
+      if (qe <= qs) {
+        // offsets that end before n_active or do not ascend: the rest of the
+        // group belongs to no cluster; reported, empty lists, loop ends
+        for (int64_t r = qs * cap + tid; r < g1 * cap; r += kPertThreads) lists[r] = -1;
+        for (int64_t r = qs + tid; r < g1; r += kPertThreads) counts[r] = 0;
+        if (tid == 0)
+          __hip_atomic_fetch_or(s.status, (int32_t)ST_INDEX, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        break;
+      }
       const double eps2 = s.eps[c] * s.eps[c];
       const double t = thr[c];
       // this wavefront's entries of the cluster

@@ -112,3 +112,26 @@ def test_perturbers_edge_cases():
     assert sim.status() == nb.NBODY_E_INDEX
     assert counts.cpu().numpy()[0] == 0 and np.all(lists.cpu().numpy() == -1)
     sim.close()
+
+
+def test_perturbers_offsets_ending_before_the_list():
+    """Active offsets whose last entry is below n_active: the entries past
+    it belong to no cluster, are reported and get empty lists; the one
+    entry inside matches the oracle."""
+    import torch
+
+    import paper_0711_0643_amd as nb
+
+    m, x, v, coff, eps = icgen.ensemble(2, 9, 100, 300)
+    sim = nb.Sim(m, x, v, eps, cluster_offsets=coff, precision=0)
+    act = np.array([3, 5, 7], dtype=np.int32)
+    lists, counts = sim.perturbers(act, [0.05, 0.05], active_offsets=np.array([0, 1, 1], dtype=np.int64),
+                                   max_pert=32)
+    torch.cuda.synchronize()
+    assert sim.status() == nb.NBODY_E_INDEX
+    lists, counts = lists.cpu().numpy(), counts.cpu().numpy()
+    b, e = int(coff[0]), int(coff[1])
+    rl, rc = oracle.perturbers(m[b:e], x[:, b:e], eps[0], 0.05, np.array([3 - b], dtype=np.int32), 32)
+    assert counts[0] == rc[0] and np.array_equal(np.where(lists[0] >= 0, lists[0] - b, -1), rl[0])
+    assert np.all(counts[1:] == 0) and np.all(lists[1:] == -1)
+    sim.close()
