@@ -43,9 +43,10 @@ __global__ void __launch_bounds__(256) stage_by_id_kernel(DevState s) {
 // taken cluster by cluster (entries are cluster-major, so a group meets few
 // clusters); each wavefront holds kPertGroup / 4 of them.  The cluster's
 // id-ordered j-data pass through LDS in rounds of kPertRound ids, read by
-// every entry of the group.  Lane l tests ids u * 64 + l of the round
-// (consecutive lanes, consecutive LDS words), and a ballot per u places the
-// passing ids in ascending order.
+// every wavefront of the group.  Lane l reads ids u * 64 + l of the round
+// (consecutive lanes, consecutive LDS words) and tests each against all of
+// its wavefront's entries; a ballot per id and entry places the passing ids
+// in ascending order.
 __global__ void __launch_bounds__(kPertThreads)
 perturbers_kernel(DevState s, const int32_t* __restrict__ ids, const int64_t* __restrict__ aoff, int64_t n_active,
                   const double* __restrict__ thr, int32_t cap, int32_t* __restrict__ lists,
@@ -117,20 +118,27 @@ perturbers_kernel(DevState s, const int32_t* __restrict__ ids, const int64_t* __
           tM[k] = in ? M[j] : 0.0;
         }
         __syncthreads();
+        for (int u = 0; u < kPertRound / 64; ++u) {
+          // each LDS record is read once and tested against every entry of
+          // the wavefront
+          const int l = u * 64 + lane;
+          const int64_t j = j0 + l;
+          const double xj = tX[l], yj = tY[l], zj = tZ[l], mj = tM[l];
+          // the tests of all entries first, without branches, so that their
+          // divisions overlap (padding past the cluster and the entry itself
+          // may give inf or NaN there; the conditions drop them)
+          bool pass[kPerWave];
 #pragma unroll
-        for (int k = 0; k < kPerWave; ++k) {
-          if (!on[k]) continue;  // uniform within the wavefront
-          for (int u = 0; u < kPertRound / 64; ++u) {
-            const int l = u * 64 + lane;
-            const int64_t j = j0 + l;
-            bool pass = false;
-            if (j < e && j != id[k]) {
-              const double r2 = softened_r2(tX[l] - xi[k], tY[l] - yi[k], tZ[l] - zi[k], eps2);
-              pass = tM[l] / r2 > t;
-            }
-            const uint64_t mask = __ballot(pass);
+          for (int k = 0; k < kPerWave; ++k) {
+            const double term = mj / softened_r2(xj - xi[k], yj - yi[k], zj - zi[k], eps2);
+            pass[k] = on[k] & (j < e) & (j != id[k]) & (term > t);
+          }
+#pragma unroll
+          for (int k = 0; k < kPerWave; ++k) {
+            if (!on[k]) continue;  // uniform within the wavefront
+            const uint64_t mask = __ballot(pass[k]);
             const int at = found[k] + __popcll(mask & below);
-            if (pass && at < cap) lists[q[k] * cap + at] = (int32_t)j;
+            if (pass[k] && at < cap) lists[q[k] * cap + at] = (int32_t)j;
             found[k] += __popcll(mask);
           }
         }
