@@ -446,6 +446,27 @@ def integration_evidence():
         "oracle_rel_energy_drift": ref_drift, "oracle_block_steps": c3["block_steps"]}
     log(f"c3 run: {out['c3_plummer_n65536_mixed_to_t0.25']}")
 
+    # the same run with the switch pred_in_force off and on (the force pass
+    # predicts the j-records of one-chunk blocks): time per block step, and
+    # whether the two final states are bitwise equal
+    walls, states = {}, {}
+    for pif in (0, 1):
+        sim = nb.Sim(m, x, v, c3["eps"], precision=nb.MIXED)
+        sim.set_tuning(pred_in_force=pif)
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        sim.run(c3["t_end"], chunk=512)
+        torch.cuda.synchronize()
+        walls[pif] = time.perf_counter() - w0
+        _, fsteps, _ = sim.progress()
+        states[pif] = sim.get_state()
+        sim.close()
+    same = states[0] == states[1]
+    out["c3_pred_in_force"] = {
+        "us_per_block_step_off": round(walls[0] / fsteps[0] * 1e6, 2),
+        "us_per_block_step_on": round(walls[1] / fsteps[0] * 1e6, 2), "state_bitwise_equal": bool(same)}
+    log(f"c3 pred_in_force: {out['c3_pred_in_force']}")
+
     # C4: the 256-cluster ensemble, mixed, to t = 1/2 (default tuning)
     c4 = g["C4"]
     m, x, v, coff, eps = icgen.ensemble(c4["n_clusters"], c4["master_seed"])
@@ -634,7 +655,7 @@ def main():
             "unit": "TFLOP/s",
             "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
             "traffic": recorded_traffic(),
-            "kernel": "nb::force_kernel<3, false, true, false, true, 32, 4, 256> (mixed tile-relative, no potential, "
+            "kernel": "nb::force_kernel<3, false, true, false, true, 32, 4, 256, false> (mixed tile-relative, no potential, "
                       "near pairs, lean; FP32 window 32, 4 waves per SIMD, 256-record j-tiles)",
             "flops_per_interaction": FLOPS_ACC_JERK,
             "flop_count_rule": "algorithmic acc + jerk without the potential (FMA = 2, rsqrt = 1); 42 with it",

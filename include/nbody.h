@@ -335,7 +335,20 @@ NBODY_API nbody_status nbody_get_layout(const nbody_ctx *ctx, nbody_layout *out)
  *                 needs no scratch memory; results change at rounding level
  *                 with the window and the tile).  Other passes use their
  *                 own fixed build.
- *   reserved: must be 0.
+ *   pred_in_force: 0 (default) or 1.  With 1, a block step whose block
+ *                 fills a single i-chunk of a layout that splits j over
+ *                 lanes (small blocks) predicts only the block's members in
+ *                 the selection, and the force pass predicts each j-record
+ *                 from x, v, a, k and t as it loads it (Sect. 2.1: the
+ *                 prediction may run on the accelerator).  Same arithmetic,
+ *                 so the results are bitwise those of 0.  Applies to
+ *                 nbody_step in the FP64 format, and in the tile-relative
+ *                 format where its default build runs (near test on, every
+ *                 cluster softened, default window, waves and tile or the
+ *                 potential on) or only the j-split layouts can occur;
+ *                 elsewhere it has no effect.  Direct nbody_force calls
+ *                 always read the stored prediction.  Other values:
+ *                 NBODY_E_INVAL.
  * In the tile-relative format the mixed arithmetic runs in the
  * one-lane-per-i layout (blocks from min_block[1] on); the layouts that
  * split j over lanes (small blocks, latency-bound) run the FP64 arithmetic,
@@ -354,7 +367,7 @@ typedef struct {
     int32_t window;
     int32_t waves;
     int32_t tile;
-    int32_t reserved;
+    int32_t pred_in_force;
 } nbody_tuning;
 NBODY_API nbody_status nbody_get_tuning(const nbody_ctx *ctx, nbody_tuning *out);
 NBODY_API nbody_status nbody_set_tuning(nbody_ctx *ctx, const nbody_tuning *t);

@@ -62,7 +62,7 @@ struct Layout {
   size_t coff, eps, cid, ch_cluster, ch_begin, cl_ch, order, slot_of, tmeta, ulist;
   size_t m, x, v, a, k, t, dt, xp, vp, pot, jr;
   size_t tpred, tnow, inter, steps, cm2, cm2n, acount, umin, ucnt, act, aoff, plan, offs, ctl, part, fout, pid, status,
-      eout;
+      eout, tpstamp;
   size_t total;
   int64_t rows_cap;
   int64_t nch_max;
@@ -121,6 +121,7 @@ Layout make_layout(int64_t n, int32_t nc) {
   L.pid = take(8 * 4 * N);
   L.status = take(4);
   L.eout = take(64 * C);
+  L.tpstamp = take(8 * (size_t)L.nch_max);
   L.total = o;
   return L;
 }
@@ -228,6 +229,7 @@ struct nbody_ctx {
   // (eps^2 representable, largest m / eps^3 far from overflow): the lean
   // tile-relative build may run
   bool lean_ok = false;
+  int pif = 0;  // fused predictor requested (nbody_tuning.pred_in_force)
   // this device's copy of the static scratch (nbody_force_noalloc), looked
   // up at init with the context's device current; nullptr if unavailable
   double* scratch = nullptr;
@@ -249,6 +251,16 @@ constexpr int32_t kMaxPerturbers = 256;
 
 int force_mode(const nbody_ctx* c) { return c->p.precision == NBODY_FP64 ? kF64 : c->mixed_mode; }
 
+bool split_only(const nbody_ctx* c, int64_t n_active);
+
+// Whether the step pipeline runs the fused predictor: requested, and a
+// force build with it exists for the current settings (the device flag the
+// selection reads is set from this, so selection and force pass agree).
+bool pif_active(const nbody_ctx* c) {
+  return c->pif != 0 && has_pif_build(force_mode(c), c->p.compute_pot != 0, c->ctl.near_tau > 0.0,
+                                      split_only(c, c->n), c->lean_ok, c->kwindow, c->kwaves, c->ktile);
+}
+
 nbody_status upload_ctl(nbody_ctx* c) {
   c->ctl.eta = c->p.eta;
   c->ctl.eta_init = c->p.eta_init;
@@ -258,6 +270,7 @@ nbody_status upload_ctl(nbody_ctx* c) {
   // the tile-relative format has no two-i-per-lane build: plan without it
   Ctl up = c->ctl;
   if (force_mode(c) == kTR) up.vmin[0] = up.vmin_small[0] = INT32_MAX;  // above any block (<= 2^30)
+  up.pred_in_force = pif_active(c) ? 1 : 0;
   // host-owned fields only: the rsq_* fields at the end are written on the device
   HIP_OK(hipMemcpyAsync(c->ws + c->L.ctl, &up, offsetof(Ctl, rsq_scale3), hipMemcpyHostToDevice, c->stream));
   HIP_OK(hipStreamSynchronize(c->stream));  // `up` is host memory the copy reads
@@ -324,10 +337,11 @@ constexpr int kStepsPerGraph = 32;
 hipError_t capture_steps(nbody_ctx* c, int steps, int par0, hipGraph_t* g) {
   const DevState& s = c->s;
   const int mode = force_mode(c);
-  // block sizes are counted where they decide the tile frames: the
+  // block sizes are counted where they decide the tile frames (the
   // tile-relative format with some cluster that can reach its
-  // one-lane-per-i layout
-  const bool counting = mode == kTR && !split_only(c, s.n);
+  // one-lane-per-i layout) or the fused predictor
+  const bool pif = pif_active(c);
+  const bool counting = (mode == kTR && !split_only(c, s.n)) || pif;
   hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed);
   if (e != hipSuccess) return e;
   for (int k = 0; k < steps && e == hipSuccess; ++k) {
@@ -335,7 +349,7 @@ hipError_t capture_steps(nbody_ctx* c, int steps, int par0, hipGraph_t* g) {
     e = launch_select(s, c->target_items, mode, par, counting, c->cap_stream);
     if (e == hipSuccess)
       e = launch_force(s, mode, c->p.compute_pot != 0, c->ctl.near_tau > 0.0, split_only(c, s.n), c->lean_ok, s.act,
-                       c->grid, par, c->target_items, c->cap_stream, c->kwindow, c->kwaves, c->ktile);
+                       c->grid, par, c->target_items, c->cap_stream, c->kwindow, c->kwaves, c->ktile, pif);
     if (e == hipSuccess)
       e = launch_reduce_correct_step(s, c->p.compute_pot != 0, par, c->target_items, counting, c->cap_stream);
   }
@@ -527,6 +541,7 @@ nbody_status nbody_init(nbody_ctx** out, int64_t n_total, int32_t n_clusters, co
   s.fout = (double*)(w + L.fout);
   s.pid = (double*)(w + L.pid);
   s.status = (int32_t*)(w + L.status);
+  s.tpstamp = (double*)(w + L.tpstamp);
 
   c->ctl.vmin[0] = 1 << 30;  // two i per lane: off (one i per lane is faster on gfx950)
   c->ctl.vmin[1] = 1024;
@@ -915,7 +930,7 @@ nbody_status nbody_get_tuning(const nbody_ctx* c, nbody_tuning* t) {
   t->window = c->kwindow;
   t->waves = c->kwaves;
   t->tile = c->ktile;
-  t->reserved = 0;
+  t->pred_in_force = c->pif;
   return NBODY_OK;
 }
 
@@ -933,7 +948,7 @@ nbody_status nbody_set_tuning(nbody_ctx* c, const nbody_tuning* t) {
     if (i > 0 && t->min_block[i - 1] < t->min_block[i]) return NBODY_E_INVAL;
     if (i > 0 && t->small_min_block[i - 1] < t->small_min_block[i]) return NBODY_E_INVAL;
   }
-  if (t->small_cluster_n < 0 || t->reserved != 0) return NBODY_E_INVAL;
+  if (t->small_cluster_n < 0 || (t->pred_in_force != 0 && t->pred_in_force != 1)) return NBODY_E_INVAL;
   if ((t->window != 16 && t->window != 32 && t->window != 64) || t->waves < 2 || t->waves > 5) return NBODY_E_INVAL;
   if ((t->tile != 128 && t->tile != kTile) || (t->tile == 128 && t->window == 64)) return NBODY_E_INVAL;
   c->target_items = t->target_items;
@@ -950,6 +965,7 @@ nbody_status nbody_set_tuning(nbody_ctx* c, const nbody_tuning* t) {
   for (int i = 0; i < kNumVariants - 1; ++i) c->ctl.vmin[i] = t->min_block[i];
   for (int i = 0; i < kNumVariants - 1; ++i) c->ctl.vmin_small[i] = t->small_min_block[i];
   c->ctl.small_n = t->small_cluster_n;
+  c->pif = t->pred_in_force;
   destroy_graph(c);  // the captured step bakes in grid, plan target and format
   // the step pipeline's carried-over state (with one cluster, the previous
   // step's plan is recomputed from its count) assumes the plan settings it

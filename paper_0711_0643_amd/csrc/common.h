@@ -81,7 +81,9 @@ struct Ctl {
   double t_end;
   double eta, eta_init, dt_max, dt_min;
   int32_t compute_pot;
-  int32_t pad;
+  // blocks that fill a single i-chunk of a layout splitting j over lanes
+  // are predicted in the force pass (fused_prediction)
+  int32_t pred_in_force;
   int64_t total_items;  // items of the current plan
   int64_t total_rows;   // partial rows of the current plan
   int64_t total_red;    // reduce work units of the current plan
@@ -155,6 +157,8 @@ struct DevState {
   double* fout;    // [7][n] reduced force of internal passes (a, k, pot)
   double* pid;     // [4][n] perturber pass: predicted x, y, z and mass in particle-id order
   int32_t* status;
+  double* tpstamp;  // [nch] per chunk: time of the stored prediction (x_p, v_p) of all its particles, NaN
+                    // when the selection predicted only the block's members (the force pass then predicts)
 };
 
 // Layout and slicing of a cluster of nn particles whose block has na
@@ -224,6 +228,25 @@ __device__ inline void load_thresholds(const Ctl* ctl, int32_t* vmin_all) {
     vmin_all[kNumVariants - 1 + v] = ctl->vmin_small[v];
   }
   vmin_all[2 * (kNumVariants - 1)] = (int32_t)(ctl->small_n < INT32_MAX ? ctl->small_n : INT32_MAX);
+}
+
+// Whether a block of layout `variant` in `chunks` i-chunks takes the fused
+// predictor (Sect. 2.1: the prediction may run on the accelerator): the
+// selection predicts only the block's members and the force pass forms each
+// j-record from x, v, a, k and t itself.  Only the layouts that split j over
+// lanes, and only a block that fills a single i-chunk, so that every j is
+// predicted once per slice.
+__host__ __device__ inline bool fused_prediction(int32_t enabled, int variant, int64_t chunks) {
+  return enabled != 0 && variant >= 2 && chunks == 1;
+}
+
+// Hermite predictor of one coordinate to h = t_p - t (Sect. 2.1, predictor
+// equations); every kernel that predicts calls this one expression, so
+// that all of them round alike.
+__device__ __forceinline__ void hermite_predict(double x, double v, double a, double k, double h, double& xp,
+                                                double& vp) {
+  xp = x + h * (v + h * (0.5 * a + h * (k * (1.0 / 6.0))));
+  vp = v + h * (a + h * (0.5 * k));
 }
 
 // Reduce work units of a cluster's plan.

@@ -55,9 +55,44 @@ static hipError_t launch_family(const ForceLaunch& L, int mode, bool pot, bool n
   return hipGetLastError();
 }
 
+// The builds with the fused predictor (PIF): FP64 in both families, and the
+// default lean tile-relative build (whose j-split layouts run FP64); the
+// host switches the predictor on only where one of these runs.
+template <int MODE, bool POT, bool SPLIT, bool LEAN, int WPE>
+static void launch_pif(const ForceLaunch& L) {
+  hipLaunchKernelGGL((force_kernel<MODE, POT, MODE == kTR, SPLIT, LEAN, 32, WPE, kTile, true>), dim3(L.grid),
+                     dim3(kForceThreads), 0, L.st, L.s, L.act, L.par, L.target_items);
+}
+
+static hipError_t launch_family_pif(const ForceLaunch& L, int mode, bool pot, bool near, bool split) {
+  const bool tr_split = mode == kTR && split;
+  if (mode == kF64 || tr_split) {
+    if (split) {
+      if (pot) launch_pif<kF64, true, true, false, 4>(L);
+      else launch_pif<kF64, false, true, false, 4>(L);
+    } else {
+      if (pot) launch_pif<kF64, true, false, false, 3>(L);
+      else launch_pif<kF64, false, false, false, 3>(L);
+    }
+  } else if (mode == kTR && near && L.lean && (pot || (L.window == 32 && L.waves == 4 && L.tile == kTile))) {
+    if (pot) launch_pif<kTR, true, false, true, 3>(L);
+    else launch_pif<kTR, false, false, true, 4>(L);
+  } else {
+    return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+bool has_pif_build(int mode, bool pot, bool near, bool split, bool lean, int window, int waves, int tile) {
+  const bool lean_default = near && lean && (pot || (window == 32 && waves == 4 && tile == kTile));
+  return mode == kF64 || (mode == kTR && (split || lean_default));
+}
+
 hipError_t launch_force(const DevState& s, int mode, bool pot, bool near, bool split, bool lean, const int32_t* act,
-                        int grid, int par, int64_t target_items, hipStream_t st, int window, int waves, int tile) {
+                        int grid, int par, int64_t target_items, hipStream_t st, int window, int waves, int tile,
+                        bool pif) {
   const ForceLaunch L{s, act, grid, par, lean, target_items, st, window, waves, tile};
+  if (pif) return launch_family_pif(L, mode, pot, near, split);
   return split ? launch_family<true>(L, mode, pot, near) : launch_family<false>(L, mode, pot, near);
 }
 

@@ -175,6 +175,25 @@ __device__ __forceinline__ RecP64 load_p64(const DevState& s, int64_t i) {
   return r;
 }
 
+// FP64 j-record of the fused predictor: particle j predicted to tp from its
+// state, with the arithmetic of the selection's predictor.
+__device__ __forceinline__ RecF64 predict_rec(const DevState& s, int64_t j, double tp) {
+  const int64_t n = s.n;
+  const double h = tp - s.t[j];
+  double p[3], q[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int64_t o = d * n + j;
+    hermite_predict(s.x[o], s.v[o], s.a[o], s.k[o], h, p[d], q[d]);
+  }
+  RecF64 r;
+  r.x = p[0]; r.y = p[1]; r.z = p[2];
+  r.m = s.m[j];
+  r.vx = q[0]; r.vy = q[1]; r.vz = q[2];
+  r.pad = 0.0;
+  return r;
+}
+
 // 1/sqrt(r2) in FP64: hardware estimate, then y <- y + y e (1/2 + 3e/8) with
 // e = 1 - r2 y^2 (third-order Newton-type step for r2^(-1/2)).
 __device__ __forceinline__ double rsqrt_f64(double r2) {
@@ -611,7 +630,8 @@ __device__ __forceinline__ int find_cluster(const Plan* plan, int nc, int64_t it
 // adds exactly nothing to a and k, and its window is always redone in FP64
 // (which skips it); padding records sit at 1e15, where every term is zero.
 // Without the masked copy of the sweep the kernel needs far fewer registers.
-template <int MODE, int JL, int IPT, bool POT, bool NEAR, bool LEAN = false, int FW = 32, int TJ = kTile>
+template <int MODE, int JL, int IPT, bool POT, bool NEAR, bool LEAN = false, int FW = 32, int TJ = kTile,
+          bool PIF = false>
 __device__ void run_item(const DevState& s, const int32_t* __restrict__ act, const Plan& P, int c,
                          int64_t local_item, unsigned char* lds, float* wmax) {
   static_assert(JL == 1 || IPT == 1, "several i per lane only with one lane per i");
@@ -686,6 +706,15 @@ __device__ void run_item(const DevState& s, const int32_t* __restrict__ act, con
   const int64_t j_begin = c_begin + (int64_t)slice * P.slice_len;
   int64_t j_end = j_begin + P.slice_len;
   if (j_end > c_end) j_end = c_end;
+  // PIF builds (step pipeline with the fused predictor on): the FP64
+  // records of a block that takes the fused predictor (j-split layouts) are
+  // predicted here to the cluster's prediction time
+  bool fused = false;
+  double tp = 0.0;
+  if constexpr (PIF && MODE == kF64 && JL > 1) {
+    fused = fused_prediction(s.ctl->pred_in_force, P.variant, P.chunks);
+    if (fused) tp = s.tpred[c];
+  }
   // the frames must have been formed at the cluster's prediction time (the
   // selection forms them only for blocks that read them, all of a cluster's
   // or none): checked on the item's first tile, off the sweep's registers
@@ -736,7 +765,13 @@ __device__ void run_item(const DevState& s, const int32_t* __restrict__ act, con
         tile64[tid] = q;
         mrec = r.m;
       } else {
-        const Rec rec = loads ? load_rec<MODE>(s, j) : zero_rec<MODE>();
+        Rec rec;
+        if constexpr (PIF && MODE == kF64 && JL > 1) {
+          rec = zero_rec<MODE>();
+          if (loads) rec = fused ? predict_rec(s, j, tp) : load_rec<MODE>(s, j);
+        } else {
+          rec = loads ? load_rec<MODE>(s, j) : zero_rec<MODE>();
+        }
         tile[tid] = rec;
         mrec = (float)rec.m;
       }
@@ -827,6 +862,15 @@ __device__ void run_item(const DevState& s, const int32_t* __restrict__ act, con
       sweep_tile<MODE, PER, IPT, false, POT, NEAR, false, FW, TJ>(s, tile, tile64, wmax, jl * PER, own, jend, i_glob, I,
                                                               xi64, gsel, ksel, mthr, eps2d, eps2f, ca, cp, A);
   }
+  // PIF builds: the other FP64 records are the stored prediction, which the
+  // selection left complete unless it decided this block fused, so the
+  // first tile's chunk must carry the cluster's prediction time (checked
+  // after the sweep, off the latency of its first tile)
+  if constexpr (PIF && MODE == kF64) {
+    if (!fused && tid == 0 && j_begin < j_end &&
+        s.tpstamp[s.cl_ch[c] + (int)((j_begin - c_begin) / kTile)] != s.tpred[c])
+      __hip_atomic_fetch_or(s.status, (int32_t)ST_STATE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
 
   const int64_t rows_cap = s.rows_cap;
   const int64_t row0 = P.slot_base + (int64_t)slice * P.n_act;
@@ -882,11 +926,12 @@ __device__ void run_item(const DevState& s, const int32_t* __restrict__ act, con
 // FW: the FP32 window (16, 32 or 64 pairs); WPE: the occupancy the
 // compiler is held to (waves per SIMD); TJ: j-records per LDS tile (128 or
 // 256; a 128-record tile uses half the threads to load and half a selection
-// chunk's frame).  Builds other than FW = 32, TJ = 256 with the default
-// occupancy are made only of the lean tile-relative kernel without the
-// potential (the autotuner's candidates).
+// chunk's frame); PIF: the fused predictor (launched only by the step
+// pipeline, and only while it is on).  Builds other than FW = 32, TJ = 256
+// with the default occupancy are made only of the lean tile-relative kernel
+// without the potential (the autotuner's candidates).
 template <int MODE, bool POT, bool NEAR, bool SPLIT, bool LEAN, int FW = 32, int WPE = (SPLIT ? 4 : 3),
-          int TJ = kTile>
+          int TJ = kTile, bool PIF = false>
 __global__ void __launch_bounds__(kForceThreads) __attribute__((amdgpu_waves_per_eu(WPE)))
 force_kernel(DevState s, const int32_t* __restrict__ act, int par, int64_t target_items) {
   static_assert(FW == 16 || FW == 32 || FW == 64, "FP32 window of 16, 32 or 64 pairs");
@@ -919,9 +964,9 @@ force_kernel(DevState s, const int32_t* __restrict__ act, int par, int64_t targe
     const int64_t local = item - P.item_off;
     if constexpr (SPLIT) {
       switch (P.variant) {
-        case 2: run_item<SM, 4, 1, POT, SNEAR, false, FW, TJ>(s, act, P, c, local, lds, wmax); break;
-        case 3: run_item<SM, 16, 1, POT, SNEAR, false, FW, TJ>(s, act, P, c, local, lds, wmax); break;
-        case 4: run_item<SM, 64, 1, POT, SNEAR, false, FW, TJ>(s, act, P, c, local, lds, wmax); break;
+        case 2: run_item<SM, 4, 1, POT, SNEAR, false, FW, TJ, PIF>(s, act, P, c, local, lds, wmax); break;
+        case 3: run_item<SM, 16, 1, POT, SNEAR, false, FW, TJ, PIF>(s, act, P, c, local, lds, wmax); break;
+        case 4: run_item<SM, 64, 1, POT, SNEAR, false, FW, TJ, PIF>(s, act, P, c, local, lds, wmax); break;
         default:
           if (threadIdx.x == 0)
             __hip_atomic_fetch_or(s.status, (int32_t)ST_STATE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -933,18 +978,18 @@ force_kernel(DevState s, const int32_t* __restrict__ act, int par, int64_t targe
       // per launch): the host plans it with that layout's threshold above
       // any block size, so layout 0 never occurs here
       switch (P.variant) {
-        case 1: run_item<MODE, 1, 1, POT, NEAR, LEAN, FW, TJ>(s, act, P, c, local, lds, wmax); break;
-        case 2: run_item<SM, 4, 1, POT, SNEAR, false, FW, TJ>(s, act, P, c, local, lds, wmax); break;
-        case 3: run_item<SM, 16, 1, POT, SNEAR, false, FW, TJ>(s, act, P, c, local, lds, wmax); break;
-        default: run_item<SM, 64, 1, POT, SNEAR, false, FW, TJ>(s, act, P, c, local, lds, wmax); break;
+        case 1: run_item<MODE, 1, 1, POT, NEAR, LEAN, FW, TJ, PIF>(s, act, P, c, local, lds, wmax); break;
+        case 2: run_item<SM, 4, 1, POT, SNEAR, false, FW, TJ, PIF>(s, act, P, c, local, lds, wmax); break;
+        case 3: run_item<SM, 16, 1, POT, SNEAR, false, FW, TJ, PIF>(s, act, P, c, local, lds, wmax); break;
+        default: run_item<SM, 64, 1, POT, SNEAR, false, FW, TJ, PIF>(s, act, P, c, local, lds, wmax); break;
       }
     } else {
       switch (P.variant) {
-        case 0: run_item<MODE, 1, 2, POT, NEAR, LEAN, FW, TJ>(s, act, P, c, local, lds, wmax); break;
-        case 1: run_item<MODE, 1, 1, POT, NEAR, LEAN, FW, TJ>(s, act, P, c, local, lds, wmax); break;
-        case 2: run_item<SM, 4, 1, POT, SNEAR, false, FW, TJ>(s, act, P, c, local, lds, wmax); break;
-        case 3: run_item<SM, 16, 1, POT, SNEAR, false, FW, TJ>(s, act, P, c, local, lds, wmax); break;
-        default: run_item<SM, 64, 1, POT, SNEAR, false, FW, TJ>(s, act, P, c, local, lds, wmax); break;
+        case 0: run_item<MODE, 1, 2, POT, NEAR, LEAN, FW, TJ, PIF>(s, act, P, c, local, lds, wmax); break;
+        case 1: run_item<MODE, 1, 1, POT, NEAR, LEAN, FW, TJ, PIF>(s, act, P, c, local, lds, wmax); break;
+        case 2: run_item<SM, 4, 1, POT, SNEAR, false, FW, TJ, PIF>(s, act, P, c, local, lds, wmax); break;
+        case 3: run_item<SM, 16, 1, POT, SNEAR, false, FW, TJ, PIF>(s, act, P, c, local, lds, wmax); break;
+        default: run_item<SM, 64, 1, POT, SNEAR, false, FW, TJ, PIF>(s, act, P, c, local, lds, wmax); break;
       }
     }
     __syncthreads();  // LDS is reused by the next item

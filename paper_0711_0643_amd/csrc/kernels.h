@@ -25,9 +25,12 @@ constexpr int kSelThreads = 256;
 // waves, tile: FP32 window (16, 32, 64), waves per SIMD (2 to 5) and
 // j-records per LDS tile (128 or 256) of the lean tile-relative kernel
 // without the potential; other kernels use 32, their own occupancy and 256.
+// pif: the build with the fused predictor (step pipeline only; there must
+// be one for these arguments: has_pif_build).
 hipError_t launch_force(const DevState& s, int mode, bool pot, bool near, bool split, bool lean, const int32_t* act,
                         int grid, int par, int64_t target_items, hipStream_t st, int window = 32, int waves = 4,
-                        int tile = 256);
+                        int tile = 256, bool pif = false);
+bool has_pif_build(int mode, bool pot, bool near, bool split, bool lean, int window, int waves, int tile);
 
 // Plan the force pass for the active offsets `aoff` (device, nc+1) of an
 // active list of at most n_act_bound entries.  target_items: work items aimed

@@ -81,9 +81,8 @@ __device__ __forceinline__ void predict_from(const DevState& s, int64_t i, const
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     const int64_t o = d * n + i;
-    const double x = in.x[d], v = in.v[d], a = in.a[d], k = in.k[d];
-    const double xp = x + h * (v + h * (0.5 * a + h * (k * (1.0 / 6.0))));
-    const double vp = v + h * (a + h * (0.5 * k));
+    double xp, vp;
+    hermite_predict(in.x[d], in.v[d], in.a[d], in.k[d], h, xp, vp);
     xo[d] = xp;
     vo[d] = vp;
     s.xp[o] = xp;
@@ -182,6 +181,7 @@ __global__ void __launch_bounds__(kSelThreads) predict_all_kernel(DevState s) {
     m = s.m[i];
   }
   tile_frame(s, ch, have, xp, vp, m, tp);
+  if (threadIdx.x == 0) s.tpstamp[ch] = tp;
 }
 
 hipError_t launch_predict_all(const DevState& s, hipStream_t st) {
@@ -889,12 +889,12 @@ __global__ void __launch_bounds__(kSelThreads) select_init_kernel(DevState s, in
   }
 }
 
-// Whether a block of na members of cluster c takes a one-lane-per-i layout
-// (the same decision as the plan's).
-__device__ __forceinline__ bool takes_one_lane_layout(const DevState& s, int c, int64_t na) {
+// Layout of a block of na members of cluster c (the same decision as the
+// plan's).
+__device__ __forceinline__ int block_variant(const DevState& s, int c, int64_t na) {
   int32_t vmin_all[2 * (kNumVariants - 1) + 1];
   load_thresholds(s.ctl, vmin_all);
-  return plan_variant(na, s.coff[c + 1] - s.coff[c], vmin_all) <= 1;
+  return plan_variant(na, s.coff[c + 1] - s.coff[c], vmin_all);
 }
 
 template <bool COUNT>
@@ -969,13 +969,22 @@ __global__ void __launch_bounds__(kSelThreads) select_kernel(DevState s, int mod
   const bool frozen = *s.status != 0;
   const bool advancing = !frozen && tsys <= s.ctl->t_end;
   const bool member = have && advancing && tt == tsys;
+  // with the block size known: its layout, and whether the force pass
+  // predicts its j-records itself (fused_prediction; the formats whose
+  // j-split layouts read only x_p, v_p), in which case only the members
+  // are predicted here
+  const int var = COUNT ? block_variant(s, c, nblock) : 0;
+  const int64_t iwg = variant_iwg(var);
+  const bool fuse = COUNT && advancing && (mode == kF64 || mode == kTR) &&
+                    fused_prediction(s.ctl->pred_in_force, var, (nblock + iwg - 1) / iwg);
   double xo[3] = {0.0, 0.0, 0.0}, vo[3] = {0.0, 0.0, 0.0};
-  if (have && advancing) predict_from(s, i, ahead ? pin : load_pred(s, i), tsys, mode, member, xo, vo);
+  if (have && advancing && (member || !fuse))
+    predict_from(s, i, ahead ? pin : load_pred(s, i), tsys, mode, member, xo, vo);
   // the mixed force pass reads the tile frame of every chunk of an
   // advancing cluster (the condition is the same for the whole workgroup);
   // the tile-relative mode only when this block takes a one-lane-per-i
   // layout (its split layouts run the FP64 arithmetic)
-  if (advancing && mode != kF64 && (mode != kTR || (COUNT && takes_one_lane_layout(s, c, nblock))))
+  if (advancing && mode != kF64 && (mode != kTR || (COUNT && var <= 1)))
     tile_frame(s, ch, have, xo, vo, have ? s.m[i] : 0.0, tsys);
 
   // members, and the smallest t + dt of the others (with their number)
@@ -991,7 +1000,10 @@ __global__ void __launch_bounds__(kSelThreads) select_kernel(DevState s, int mod
     nxt[ch] = rest;
     if (COUNT) nxtn[ch] = nrest;
     base_sh = total > 0 ? atomicAdd(&s.acount[(int64_t)par * s.nc + c], (int32_t)total) : 0;
-    if (advancing && ch == s.cl_ch[c]) s.tpred[c] = tsys;
+    if (advancing) {
+      s.tpstamp[ch] = fuse ? __builtin_nan("") : tsys;
+      if (ch == s.cl_ch[c]) s.tpred[c] = tsys;
+    }
   }
   __syncthreads();
   if (member) s.act[s.coff[c] + base_sh + before] = (int32_t)i;

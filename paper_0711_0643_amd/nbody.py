@@ -113,7 +113,7 @@ class Tuning(ctypes.Structure):
         ("window", ctypes.c_int32),
         ("waves", ctypes.c_int32),
         ("tile", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("pred_in_force", ctypes.c_int32),
     ]
 
 
@@ -346,7 +346,8 @@ class Sim:
                 "mixed_format": t.mixed_format, "rsq_bias_correct": t.rsq_bias_correct,
                 "near_tau": t.near_tau, "small_cluster_n": t.small_cluster_n,
                 "small_min_block": list(t.small_min_block), "near_tau_k": t.near_tau_k,
-                "mid_tau": t.mid_tau, "window": t.window, "waves": t.waves, "tile": t.tile}
+                "mid_tau": t.mid_tau, "window": t.window, "waves": t.waves, "tile": t.tile,
+                "pred_in_force": t.pred_in_force}
 
     def set_tuning(self, **kw) -> None:
         cur = self.get_tuning()
@@ -364,6 +365,7 @@ class Sim:
         t.window = int(cur["window"])
         t.waves = int(cur["waves"])
         t.tile = int(cur["tile"])
+        t.pred_in_force = int(cur["pred_in_force"])
         t.small_cluster_n = int(cur["small_cluster_n"])
         for i in range(4):
             t.small_min_block[i] = int(cur["small_min_block"][i])
