@@ -706,14 +706,16 @@ __device__ void run_item(const DevState& s, const int32_t* __restrict__ act, con
   const int64_t j_begin = c_begin + (int64_t)slice * P.slice_len;
   int64_t j_end = j_begin + P.slice_len;
   if (j_end > c_end) j_end = c_end;
-  // PIF builds (step pipeline with the fused predictor on): the FP64
-  // records of a block that takes the fused predictor (j-split layouts) are
-  // predicted here to the cluster's prediction time
+  // PIF builds (launched only while the fused predictor is on, the device
+  // flag the selection reads being set from the same host test): the FP64
+  // records of a block that takes it (j-split layouts) are predicted here to
+  // the cluster's prediction time.  The flag is not read here: a load on
+  // this path delays the tile's loads by a memory round trip.
   bool fused = false;
   double tp = 0.0;
   if constexpr (PIF && MODE == kF64 && JL > 1) {
-    fused = fused_prediction(s.ctl->pred_in_force, P.variant, P.chunks);
-    if (fused) tp = s.tpred[c];
+    fused = fused_prediction(1, P.variant, P.chunks);
+    tp = s.tpred[c];
   }
   // the frames must have been formed at the cluster's prediction time (the
   // selection forms them only for blocks that read them, all of a cluster's
