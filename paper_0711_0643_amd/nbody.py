@@ -133,7 +133,7 @@ def lib() -> ctypes.CDLL:
         import torch  # noqa: F401
 
         if not _LIB_PATH.exists():
-            raise RuntimeError(f"{_LIB_PATH} is not built; run paper_0711_0643_amd/build.py (or __graft_entry__.build())")
+            raise RuntimeError(f"{_LIB_PATH} is not built; run paper_0711_0643_amd/build.py")
         L = ctypes.CDLL(str(_LIB_PATH))
         p, i32, i64, f64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
         st = ctypes.c_int
