@@ -26,6 +26,25 @@ __device__ __forceinline__ double softened_r2(double dx, double dy, double dz, d
   return dx * dx + dy * dy + dz * dz + eps2;
 }
 
+// fl(m / r2) > t without the division where its outcome is certain.  With
+// t and p = fl(t r2) well inside the normal range, m > fl(p (1 + 2^-40))
+// gives m / r2 > t (1 + 2^-40 - 3u) exactly, so the rounded quotient
+// exceeds t; m < fl(p (1 - 2^-40)) gives a rounded quotient below t
+// (u = 2^-53, every rounding a relative error of at most u there).
+// Otherwise (|m / (t r2) - 1| within about 2^-40, t not positive, anything
+// out of range, NaN) the rounded quotient itself decides, as the
+// definition states.
+__device__ __forceinline__ bool above_threshold(double m, double r2, double t) {
+#pragma clang fp contract(off)
+  const double p = t * r2;
+  const bool ok = p > 0x1p-1000 && p < 0x1p1000 && t > 0x1p-1000 && t < 0x1p1000;
+  const bool sure_pass = ok && m > p * (1.0 + 0x1p-40);
+  const bool sure_fail = ok && m < p * (1.0 - 0x1p-40);
+  bool pass = sure_pass;
+  if (!sure_pass && !sure_fail) pass = m / r2 > t;
+  return pass;
+}
+
 // Predicted positions and masses in particle-id order (s.pid), so that the
 // sweeps below read them coalesced in the order they test them.
 __global__ void __launch_bounds__(256) stage_by_id_kernel(DevState s) {
@@ -124,14 +143,15 @@ perturbers_kernel(DevState s, const int32_t* __restrict__ ids, const int64_t* __
           const int l = u * 64 + lane;
           const int64_t j = j0 + l;
           const double xj = tX[l], yj = tY[l], zj = tZ[l], mj = tM[l];
-          // the tests of all entries first, without branches, so that their
-          // divisions overlap (padding past the cluster and the entry itself
-          // may give inf or NaN there; the conditions drop them)
+          // the tests of all entries first (padding past the cluster and the
+          // entry itself may give inf or NaN there; the conditions drop
+          // them); a division runs only for the rare pair whose outcome the
+          // product test leaves open
           bool pass[kPerWave];
 #pragma unroll
           for (int k = 0; k < kPerWave; ++k) {
-            const double term = mj / softened_r2(xj - xi[k], yj - yi[k], zj - zi[k], eps2);
-            pass[k] = on[k] & (j < e) & (j != id[k]) & (term > t);
+            const double r2 = softened_r2(xj - xi[k], yj - yi[k], zj - zi[k], eps2);
+            pass[k] = on[k] & (j < e) & (j != id[k]) & above_threshold(mj, r2, t);
           }
 #pragma unroll
           for (int k = 0; k < kPerWave; ++k) {

@@ -135,3 +135,39 @@ def test_perturbers_offsets_ending_before_the_list():
     assert counts[0] == rc[0] and np.array_equal(np.where(lists[0] >= 0, lists[0] - b, -1), rl[0])
     assert np.all(counts[1:] == 0) and np.all(lists[1:] == -1)
     sim.close()
+
+
+def test_perturbers_thresholds_at_a_pairs_term():
+    """Thresholds at one pair's own term m_j / R^2 (formed in the same
+    operation order), one unit in the last place either side, and just
+    inside and outside a relative band of 2^-40 around it: the lists match
+    the oracle's bit for bit, the pair is left out at equality and listed
+    one unit below (the test is a strict inequality on the rounded
+    quotient)."""
+    import paper_0711_0643_amd as nb
+
+    n = 512
+    m, x, v = icgen.plummer(n, 31)
+    eps = 1.0 / n
+    i = 7
+    d = x - x[:, i:i + 1]
+    r2 = ((d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]) + eps * eps
+    terms = m / r2
+    terms[i] = -np.inf
+    j = int(np.argsort(terms)[-3])  # a pair near the top of i's list
+    t0 = float(m[j] / r2[j])
+    act = np.array([i, j, 0, n - 1], dtype=np.int32)
+    sim = nb.Sim(m, x, v, eps, precision=0)
+    cases = [t0, np.nextafter(t0, 0.0), np.nextafter(t0, np.inf), t0 * (1 + 2.0**-41), t0 * (1 - 2.0**-41),
+             t0 * (1 + 2.0**-39), t0 * (1 - 2.0**-39)]
+    banner(f"perturbers threshold at the term of pair ({i}, {j})")
+    for thr in cases:
+        lists, counts = sim.perturbers(act, [thr], max_pert=64)
+        rl, rc = oracle.perturbers(m, x, eps, thr, act, 64)
+        assert sim.status() == 0
+        assert np.array_equal(counts.cpu().numpy(), rc), thr
+        assert np.array_equal(lists.cpu().numpy(), rl), thr
+    row = lambda thr: sim.perturbers(act, [thr], max_pert=64)[0].cpu().numpy()[0]
+    assert j not in row(t0)
+    assert j in row(np.nextafter(t0, 0.0))
+    sim.close()
