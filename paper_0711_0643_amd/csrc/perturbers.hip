@@ -153,6 +153,13 @@ perturbers_kernel(DevState s, const int32_t* __restrict__ ids, const int64_t* __
             const double r2 = softened_r2(xj - xi[k], yj - yi[k], zj - zi[k], eps2);
             pass[k] = on[k] & (j < e) & (j != id[k]) & above_threshold(mj, r2, t);
           }
+          // most ids pass for none of the wavefront's entries: one ballot
+          // over all of them skips the per-entry placement (every entry's
+          // mask would be empty)
+          bool any_pass = false;
+#pragma unroll
+          for (int k = 0; k < kPerWave; ++k) any_pass |= pass[k];
+          if (__ballot(any_pass) == 0) continue;
 #pragma unroll
           for (int k = 0; k < kPerWave; ++k) {
             if (!on[k]) continue;  // uniform within the wavefront
