@@ -39,23 +39,25 @@ def _run_pair(a, b, steps, t_end):
     return fused
 
 
-def _single(n):
+def _single(n, pot=False):
     def make(nb, precision):
         m, x, v = icgen.plummer(n, 41)
-        return nb.Sim(m, x, v, 1.0 / n, precision=precision)
+        return nb.Sim(m, x, v, 1.0 / n, precision=precision, compute_pot=pot)
     return make
 
 
-@pytest.mark.parametrize("n,precision", [(4096, 0), (4096, 1), (20000, 1)])
-def test_fused_prediction_single_cluster_is_bitwise(n, precision):
-    """One Plummer cluster, FP64 and mixed; N = 20000 runs the full mixed
-    kernel (one-lane-per-i and j-split layouts), N = 4096 its j-split-only
-    build.  60 single block steps, the state compared after each; then a
-    direct force call on the stepped state."""
+@pytest.mark.parametrize("n,precision,pot", [(4096, 0, False), (4096, 1, False), (20000, 1, False),
+                                             (20000, 0, False), (20000, 1, True), (4096, 0, True)])
+def test_fused_prediction_single_cluster_is_bitwise(n, precision, pot):
+    """One Plummer cluster, FP64 and mixed, with and without the potential:
+    N = 20000 runs the full kernels (one-lane-per-i and j-split layouts),
+    N = 4096 the j-split-only builds, so every fused build runs.  60 single
+    block steps, the state compared after each; then a direct force call on
+    the stepped state."""
     import torch
 
-    banner(f"fused prediction N={n} precision={precision}")
-    a, b = _pair(_single(n), precision)
+    banner(f"fused prediction N={n} precision={precision} pot={pot}")
+    a, b = _pair(_single(n, pot), precision)
     fused = _run_pair(a, b, 60, 1.0)
     assert fused > 0, "no step took the fused predictor"
     act = a.storage_active(300)
