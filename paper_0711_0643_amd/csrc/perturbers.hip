@@ -34,14 +34,18 @@ __device__ __forceinline__ double softened_r2(double dx, double dy, double dz, d
 // Otherwise (|m / (t r2) - 1| within about 2^-40, t not positive, anything
 // out of range, NaN) the rounded quotient itself decides, as the
 // definition states.
-__device__ __forceinline__ bool above_threshold(double m, double r2, double t) {
+// t_ok: t within (2^-1000, 2^1000), the same for the whole cluster.  Nearly
+// every pair fails with certainty, so that side is tested first and the
+// rest runs only where some lane of the wavefront needs it.
+__device__ __forceinline__ bool above_threshold(double m, double r2, double t, bool t_ok) {
 #pragma clang fp contract(off)
   const double p = t * r2;
-  const bool ok = p > 0x1p-1000 && p < 0x1p1000 && t > 0x1p-1000 && t < 0x1p1000;
-  const bool sure_pass = ok && m > p * (1.0 + 0x1p-40);
-  const bool sure_fail = ok && m < p * (1.0 - 0x1p-40);
-  bool pass = sure_pass;
-  if (!sure_pass && !sure_fail) pass = m / r2 > t;
+  const bool ok = t_ok && p > 0x1p-1000 && p < 0x1p1000;
+  bool pass = false;
+  if (!(ok && m < p * (1.0 - 0x1p-40))) {  // not a certain failure
+    pass = ok && m > p * (1.0 + 0x1p-40);
+    if (!pass) pass = m / r2 > t;
+  }
   return pass;
 }
 
@@ -102,6 +106,7 @@ perturbers_kernel(DevState s, const int32_t* __restrict__ ids, const int64_t* __
       }
       const double eps2 = s.eps[c] * s.eps[c];
       const double t = thr[c];
+      const bool t_ok = t > 0x1p-1000 && t < 0x1p1000;
       // this wavefront's entries of the cluster
       int64_t q[kPerWave], id[kPerWave];
       bool on[kPerWave];
@@ -151,7 +156,7 @@ perturbers_kernel(DevState s, const int32_t* __restrict__ ids, const int64_t* __
 #pragma unroll
           for (int k = 0; k < kPerWave; ++k) {
             const double r2 = softened_r2(xj - xi[k], yj - yi[k], zj - zi[k], eps2);
-            pass[k] = on[k] & (j < e) & (j != id[k]) & above_threshold(mj, r2, t);
+            pass[k] = on[k] & (j < e) & (j != id[k]) & above_threshold(mj, r2, t, t_ok);
           }
           // most ids pass for none of the wavefront's entries: one ballot
           // over all of them skips the per-entry placement (every entry's
